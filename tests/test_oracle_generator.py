@@ -1,0 +1,275 @@
+"""Statistical and structural pins of the oracle generator as a whole.
+
+What the paper fixes: the marginal law is N(0,1) (Section 5.1); without the
+chi-square correction the pool's sum of squares is constant (Section 5.5), and
+the chi-square sample has the moments of the cubic form; taking the sample from
+the current pool couples it to the emitted sum (Section 5.5, fastnorm vs
+fastnorm2); correlations of squares are small (Sections 5.6, 5.7); mixing must
+reach every position (Section 5.4); the uniform source is used 2R times per
+pool, of the order of 1/n per normal (Section 5.8).  The negative controls
+(hazard flags of the oracle) must fail the checks that the default passes.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import oracle as O
+
+
+def moments(y):
+    y = np.asarray(y, np.float64)
+    m = y.mean()
+    d = y - m
+    v = (d * d).mean()
+    return m, v, (d**3).mean() / v**1.5, (d**4).mean() / v**2
+
+
+def gen(n, R=1, pool="f32", streams=1, **kw):
+    g = O.Generator(streams, pool_n=n, R=R, pool_dtype=pool, **kw)
+    g.seed(1)
+    return g
+
+
+# ---- continuation, batching, uniform usage -----------------------------------
+
+@pytest.mark.parametrize("pool,dt", [("f32", O.F32), ("f64", O.F64), ("f32", O.BF16),
+                                     ("f64", O.F16)])
+def test_split_fill_equals_single_fill(pool, dt):
+    n = 64
+    a = gen(n, R=2, pool=pool, streams=3)
+    b = gen(n, R=2, pool=pool, streams=3)
+    whole = a.fill([0, 1, 2], [1000, 0, 5 * (n - 1)], dt)
+    parts = []
+    for c0, c2 in ((1, 63), (62, 1), (0, 100), (937, 151)):
+        parts.append(b.fill([0, 2], [c0, c2], dt))
+    got0 = np.concatenate([p[: c0] for p, (c0, _) in zip(parts, ((1, 63), (62, 1), (0, 100),
+                                                                    (937, 151)))])
+    got2 = np.concatenate([p[c0:] for p, (c0, _) in zip(parts, ((1, 63), (62, 1), (0, 100),
+                                                                  (937, 151)))])
+    np.testing.assert_array_equal(got0.view(np.uint8), whole[:1000].view(np.uint8))
+    np.testing.assert_array_equal(got2[: 5 * (n - 1)].view(np.uint8),
+                                  whole[1000:].view(np.uint8))
+
+
+def test_results_do_not_depend_on_batching():
+    a = gen(256, R=2, streams=8)
+    b = gen(256, R=2, streams=8)
+    ya = a.fill(np.arange(8), [3000] * 8)
+    yb = b.fill([5, 2, 7, 0], [3000] * 4)
+    yb2 = b.fill([1, 3, 4, 6], [3000] * 4)
+    by_stream = {}
+    for i, s in enumerate([5, 2, 7, 0]):
+        by_stream[s] = yb[3000 * i: 3000 * (i + 1)]
+    for i, s in enumerate([1, 3, 4, 6]):
+        by_stream[s] = yb2[3000 * i: 3000 * (i + 1)]
+    for s in range(8):
+        np.testing.assert_array_equal(ya[3000 * s: 3000 * (s + 1)], by_stream[s])
+
+
+def test_mixed_pool_sizes_match_single_size_generators():
+    ns = np.array([1024, 2048, 4096, 1024], np.uint32)
+    g = O.Generator(4, pool_n=ns, R=2)
+    g.seed(7)
+    y = g.fill([0, 1, 2, 3], [5000] * 4)
+    for s, n in enumerate(ns):
+        h = O.Generator(4, pool_n=int(n), R=2)
+        h.seed(7)
+        np.testing.assert_array_equal(h.fill([s], [5000]), y[5000 * s: 5000 * (s + 1)])
+
+
+def test_duplicate_or_bad_stream_rejected():
+    g = gen(64, streams=4)
+    with pytest.raises(ValueError):
+        g.fill([1, 1], [10, 10])
+    with pytest.raises(ValueError):
+        g.fill([4], [10])
+    with pytest.raises(ValueError):
+        g.fill([0], [10], O.F64)  # binary64 output from a binary32 pool
+
+
+@pytest.mark.parametrize("n,R", [(64, 1), (1024, 2), (4096, 3)])
+def test_uniform_draws_per_pool(n, R):
+    g = gen(n, R=R, streams=2)
+    pools = 7
+    g.fill([1], [pools * (n - 1)])
+    info, _ = g.stream(1)
+    W = int(math.log2(n)) + 4
+    draws = n + 2 * W + 2 * R * pools
+    assert info.k == pools
+    assert info.xs == int(O.xorshift64(O.stream_state(1, 1), draws)[-1])
+
+
+# ---- marginal law ------------------------------------------------------------
+
+@pytest.mark.parametrize("n,R,pool,streams", [(1024, 1, "f64", 1), (4096, 2, "f32", 4),
+                                              (256, 1, "f32", 4)])
+def test_marginal_normal(n, R, pool, streams):
+    N = 1 << 20
+    g = gen(n, R=R, pool=pool, streams=streams)
+    y = g.fill(np.arange(streams), [N // streams] * streams,
+               O.F64 if pool == "f64" else O.F32).astype(np.float64)
+    m, v, sk, ku = moments(y)
+    assert abs(m) < 5 * math.sqrt(1 / N)
+    assert abs(v - 1) < 5 * math.sqrt(2 / N)
+    assert abs(sk) < 5 * math.sqrt(6 / N)
+    assert abs(ku - 3) < 5 * math.sqrt(24 / N)
+    assert stats.kstest(y, "norm").pvalue > 1e-3
+
+
+# ---- chi-square correction ---------------------------------------------------
+
+def test_rescale_follows_chi2_law():
+    n = 1024
+    g = gen(n, R=1, pool="f64", trace=True)
+    g.fill([0], [2000 * (n - 1)], O.F64)
+    tr = g.trace(0)
+    Q, S, f = tr[:, 0], tr[:, 1], tr[:, 2]
+    np.testing.assert_allclose(f * f * Q, S, rtol=1e-13)
+    N = S.size
+    assert abs(S.mean() - n) < 5 * math.sqrt(2 * n / N)
+    assert abs(S.var() / (2 * n) - 1) < 5 * math.sqrt(2 / N)
+    assert stats.kstest(S, stats.chi2(n).cdf).pvalue > 1e-3
+
+
+def test_rescale_off_sum_of_squares_is_constant():
+    n = 256
+    off = gen(n, R=1, chi2=O.CHI2_OFF, trace=True, K=0)
+    off.fill([0], [400 * (n - 1)])
+    tr = off.trace(0)
+    assert np.all(tr[:, 2] == 1.0)
+    assert np.max(np.abs(tr[:, 0] / n - 1)) < 1e-5  # constant up to rounding drift
+    on = gen(n, R=1, trace=True)
+    on.fill([0], [400 * (n - 1)])
+    scaled = on.trace(0)[:, 1]
+    assert scaled.std() > 0.5 * math.sqrt(2 * n)
+
+
+def test_rescale_off_kurtosis_defect():
+    """A pool on a fixed sphere has kurtosis 3n/(n+2); the rescale restores 3."""
+    n, N = 64, 1 << 22
+    se = math.sqrt(24 / N)
+    y_off = gen(n, R=1, chi2=O.CHI2_OFF).fill([0], [N]).astype(np.float64)
+    y_on = gen(n, R=1).fill([0], [N]).astype(np.float64)
+    ku_off, ku_on = moments(y_off)[3], moments(y_on)[3]
+    assert abs(ku_off - 3 * n / (n + 2)) < 5 * se
+    assert abs(ku_on - 3) < 5 * se
+    assert ku_on - ku_off > 10 * se
+
+
+def test_current_pool_x_couples_sample_and_emitted_sum():
+    """fastnorm's choice: corr(x^2, T) < 0; fastnorm2's choice: corr > 0 (x unseen)."""
+    n, pools = 256, 200000
+    out = {}
+    for hz in (O.HAZ_NONE, O.HAZ_CURRENT_X):
+        g = gen(n, R=1, trace=True, hazard=hz)
+        g.fill([0], [pools * (n - 1)])
+        tr = g.trace(0)
+        x, T = tr[:, 3], tr[:, 4]
+        out[hz] = np.corrcoef(x * x, T)[0, 1]
+    se = 1 / math.sqrt(pools)
+    A = O.chi2_consts(n)[0]
+    assert abs(out[O.HAZ_NONE] - A / math.sqrt(n)) < 5 * se
+    assert abs(out[O.HAZ_CURRENT_X] - (A - 1) / math.sqrt(n)) < 5 * se
+    assert out[O.HAZ_CURRENT_X] < -3 * se
+
+
+def test_successive_pool_sums_nearly_uncorrelated():
+    n, pools = 256, 40000
+    g = gen(n, R=1, trace=True)
+    g.fill([0], [pools * (n - 1)])
+    T = g.trace(0)[:, 4]
+    c = np.corrcoef(T[:-1], T[1:])[0, 1]
+    assert abs(c) < 4 / math.sqrt(pools)
+
+
+# ---- correlations of squares (Sections 5.6, 5.7) -----------------------------
+
+def test_rotation_model_squared_correlation():
+    rng = np.random.default_rng(0)
+    N = 4_000_000
+    x1, x2 = rng.standard_normal(N), rng.standard_normal(N)
+    th = rng.uniform(0, 2 * np.pi, N)
+    y1 = np.cos(th) * x1 + np.sin(th) * x2
+    v = x1 * x1 * y1 * y1
+    assert abs(v.mean() - 2.0) < 5 * v.std() / math.sqrt(N)
+
+
+def sq_autocorr(y, lag):
+    z = y.astype(np.float64) ** 2
+    return np.corrcoef(z[:-lag], z[lag:])[0, 1]
+
+
+def test_in_place_writes_keep_squared_correlation():
+    n, N = 256, 1 << 22  # N >= 10^4 n
+    good = gen(n, R=1).fill([0], [N])
+    bad = gen(n, R=1, hazard=O.HAZ_IN_PLACE).fill([0], [N])
+    se = 1 / math.sqrt(N)
+    assert sq_autocorr(bad, n - 1) > 0.15
+    assert abs(sq_autocorr(good, n - 1)) < 5 / n + 5 * se
+
+
+# ---- mixing (Section 5.4) ----------------------------------------------------
+
+def dependency_after(n, passes, hazard, seed=77):
+    u = O.xorshift64(seed, 2 * passes)
+    L = n // 4
+    dep = np.eye(n, dtype=bool)
+    full_at = None
+    for p in range(passes):
+        idx = O.gather_index(int(u[2 * p]), int(u[2 * p + 1]), n, hazard).reshape(4, L)
+        new = np.zeros_like(dep)
+        src_union = dep[idx[0]] | dep[idx[1]] | dep[idx[2]] | dep[idx[3]]  # (L, n)
+        for m in range(4):
+            dst = idx[m] if hazard == O.HAZ_IN_PLACE else m * L + np.arange(L)
+            new[dst] = src_union
+        dep = new
+        if full_at is None and dep.all():
+            full_at = p + 1
+    return dep, full_at
+
+
+@pytest.mark.parametrize("n", [64, 1024, 4096])
+def test_mixing_reaches_every_position_within_warmup(n):
+    W = int(math.log2(n)) + 4
+    dep, full_at = dependency_after(n, W, O.HAZ_NONE)
+    assert dep.all() and full_at <= W
+
+
+@pytest.mark.parametrize("hazard", [O.HAZ_GLOBAL_AFFINE, O.HAZ_SHARED_MAP])
+def test_mixing_hazards_never_mix(hazard):
+    n = 1024
+    dep, full_at = dependency_after(n, 40, hazard)
+    assert full_at is None
+    assert dep.sum(axis=1).max() == 4  # each value only ever meets its 3 partners
+
+
+# ---- precision ----------------------------------------------------------------
+
+def test_binary32_pool_tracks_binary64_pool():
+    n, pools = 4096, 40
+    g32 = gen(n, R=2, pool="f32", streams=2)
+    g64 = gen(n, R=2, pool="f64", streams=2)
+    N = pools * (n - 1)
+    y32 = g32.fill([1], [N]).astype(np.float64)
+    y64 = g64.fill([1], [N], O.F64)
+    err = np.abs(y32 - y64)
+    # The passes are orthogonal, so binary32 rounding errors (about 2^-24 per
+    # operation on values of unit size) add up like a random walk over the
+    # P passes since seeding; the output rounding adds half an ulp:
+    #   |y32 - y64| <= ulp32(y)/2 + c sqrt(P) 2^-24,
+    # with c = 8 (about 2.4 times the largest ratio seen on the CPU at
+    # n = 4096, R = 2 over 1 to 100 pools).
+    P = int(math.log2(n)) + 4 + 2 * pools
+    ulp = np.spacing(np.abs(y64).astype(np.float32)).astype(np.float64)
+    assert np.all(err <= 0.5 * ulp + 8.0 * math.sqrt(P) * 2.0**-24)
+    assert np.max(err) > 0  # the two precisions do differ
+
+
+def test_renormalisation_holds_the_norm():
+    n = 1024
+    g = gen(n, R=1, trace=True, K=16)
+    g.fill([0], [3000 * (n - 1)])
+    Q = g.trace(0)[:, 0]
+    assert np.max(np.abs(Q / n - 1)) < 1e-5
