@@ -1,0 +1,125 @@
+/*
+ * wn.h -- C ABI of the MI355X (gfx950) Wallace maximum-entropy normal
+ * generator.
+ *
+ * Method: R. P. Brent, "Some Comments on C. S. Wallace's Random Number
+ * Generators", Section 5 (5.1-5.8).  A pool of n normal variates is renewed by
+ * passes of 4x4 orthogonal transforms (Section 5.3, the matrix A1 and its
+ * sign variants) applied to quadruples chosen through affine row maps
+ * (Section 5.4); after R passes the pool's sum of squares drives a scale factor
+ * taken from an approximate chi-square sample (Section 5.5), n-1 scaled values
+ * are returned and the last one is withheld for the next pool's sample.
+ * The uniform source (Sections 3 and 5.8) is xorshift64, two draws per pass.
+ *
+ * All entry points are extern "C", take plain pointers and sizes, and never
+ * throw or abort.  Every call returns a wn_status; wn_last_error() gives a
+ * message for the calling thread's last failure.  Validation happens before
+ * anything is enqueued: on any error nothing is enqueued and the generator's
+ * state is unchanged.
+ *
+ * Asynchrony: wn_seed and wn_fill enqueue work on the given HIP stream (NULL =
+ * the default stream) and return at once.  Successive calls on one generator
+ * are ordered even across different streams (each call waits for the previous
+ * call's completion event).  A wn_gen is not thread-safe.
+ */
+#ifndef WN_H
+#define WN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wn_gen wn_gen; /* opaque; owned by the library */
+
+typedef enum {
+  WN_OK = 0,
+  WN_EINVAL = 1,  /* bad argument or configuration */
+  WN_ENOMEM = 2,  /* device or host allocation failed */
+  WN_EDEVICE = 3, /* no usable device, a HIP call failed, or a fault reported by a kernel */
+  WN_ESTATE = 4,  /* fill before seed */
+  WN_ENOTSUP = 5  /* valid but unsupported combination */
+} wn_status;
+
+typedef enum { WN_F64 = 0, WN_F32 = 1, WN_BF16 = 2, WN_F16 = 3 } wn_dtype;
+
+/* Chi-square approximation used for the rescale (Section 5.5).  CUBIC is the
+ * A(x^2-1) + sqrt(2(nu-A^2)) x + nu form with A^3 - 3 nu A + 2 nu = 0; OFF keeps
+ * the pool's constant sum of squares (the defect the rescale removes); FISHER
+ * is 2 chi2 ~ (x + sqrt(2 nu - 1))^2; WH is the Wilson-Hilferty cube. */
+typedef enum { WN_CHI2_CUBIC = 0, WN_CHI2_OFF = 1, WN_CHI2_FISHER = 2, WN_CHI2_WH = 3 } wn_chi2;
+
+typedef struct {
+  uint32_t struct_size;       /* sizeof(wn_config), for ABI versioning */
+  uint32_t num_streams;       /* >= 1; stream ids are 0 .. num_streams-1 */
+  const uint32_t *pool_n;     /* host array [num_streams] of pool sizes, or NULL */
+  uint32_t default_pool_n;    /* pool size when pool_n == NULL */
+  uint32_t passes_per_output; /* R >= 1 passes between emitted pools (Section 5.7) */
+  wn_dtype pool_dtype;        /* WN_F32 or WN_F64 */
+  wn_chi2 chi2;               /* rescale mode */
+  uint32_t renorm_period;     /* K: renormalise every K pools (0 = never) */
+  int device;                 /* HIP device ordinal */
+} wn_config;
+/* Pool sizes are powers of two in [16, 16384].  The library copies the
+ * configuration (and pool_n) during wn_create. */
+
+/* Per-stream state as returned by wn_get_stream. */
+typedef struct {
+  uint64_t xs;     /* xorshift64 state */
+  uint64_t k;      /* pools produced since seeding */
+  uint32_t n;      /* pool size */
+  uint32_t cursor; /* next pool position to emit; n-1 means the pool is used up */
+  double f;        /* scale factor of the current pool */
+  double xnext;    /* withheld, scaled value feeding the next chi-square sample */
+  double qlast;    /* binary64 sum of squares of the current pool */
+} wn_stream_info;
+
+/* Validate cfg, select the device, allocate the per-stream state in device
+ * memory (pools and 64-byte headers) and compute the chi-square constants on
+ * the host.  *out_gen receives the generator (NULL on failure).
+ * Errors: WN_EINVAL (cfg), WN_EDEVICE (no device / bad ordinal), WN_ENOMEM. */
+wn_status wn_create(const wn_config *cfg, wn_gen **out_gen);
+
+/* Seed every stream: stream s starts from xorshift64 state = output s+1 of
+ * SplitMix64 from `seed`, fills its pool from uniforms, renormalises, runs
+ * log2(n)+4 warm-up passes and renormalises again (Section 5.8: the uniform
+ * source serves for initialisation).  Enqueued on hip_stream. */
+wn_status wn_seed(wn_gen *g, uint64_t seed, void *hip_stream);
+
+/* Generate: request j asks stream streams[j] for counts[j] values; outputs are
+ * concatenated in request order into `out`, device memory owned by the caller
+ * of at least sum(counts) elements of out_dtype.  streams/counts are host
+ * arrays, read before the call returns.  Streams continue where the previous
+ * call stopped: fill(s, a) then fill(s, b) equals fill(s, a + b) bit for bit,
+ * and results never depend on batching, order or launch shape.
+ * Errors: WN_EINVAL (null pointer with a non-zero count, stream id out of
+ * range, a stream listed twice), WN_ESTATE (not seeded), WN_ENOTSUP (WN_F64
+ * output from a binary32 pool), WN_EDEVICE (HIP failure). */
+wn_status wn_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
+                  void *out, wn_dtype out_dtype, void *hip_stream);
+
+/* Wait for the generator's outstanding work and report a fault a kernel
+ * flagged since the last check (a non-finite or zero sum of squares):
+ * WN_EDEVICE with a message, else WN_OK. */
+wn_status wn_sync(wn_gen *g);
+
+/* Copy stream s's state to the host (synchronous).  pool_out (nullable)
+ * receives n values of the pool type. */
+wn_status wn_get_stream(wn_gen *g, uint32_t s, wn_stream_info *info, void *pool_out);
+
+/* Free everything the generator owns.  NULL-safe.  Waits for its work. */
+void wn_destroy(wn_gen *g);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char *wn_last_error(void);
+
+/* Library version, as major*10000 + minor*100 + patch. */
+uint32_t wn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WN_H */

@@ -1,0 +1,73 @@
+// Internal interface between the C ABI (wn_api.cpp) and the gfx950 kernels
+// (wn_kernels.hip).  Not installed; plain structs only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wn {
+
+// Per-stream header in device memory, 64 bytes.  The pool itself lives in the
+// state arena at byte offset pool_off, in natural element order.
+struct StreamHdr {
+  uint64_t xs;        // xorshift64 state
+  uint64_t k;         // pools produced since seeding
+  double f;           // scale factor of the current pool
+  double xnext;       // withheld scaled value for the next chi-square sample
+  double qlast;       // binary64 sum of squares of the current pool
+  uint64_t pool_off;  // byte offset of the pool in the arena
+  uint32_t n;         // pool size
+  uint32_t cursor;    // next pool position to emit; n-1 = used up
+  uint32_t pad[2];
+};
+static_assert(sizeof(StreamHdr) == 64, "header must stay 64 bytes");
+
+// Chi-square constants for one pool size (computed on the host).
+struct Chi2Consts {
+  double nu, A, b, fisher_root, wh_c, wh_shift;
+};
+
+// One unit of work: a stream, how many values it emits, where they go.
+struct WorkItem {
+  uint32_t stream;
+  uint32_t pad;
+  uint64_t count;
+  uint64_t out_off;  // element offset in the output
+};
+
+enum : uint32_t { kChi2Cubic = 0, kChi2Off = 1, kChi2Fisher = 2, kChi2WH = 3 };
+enum : uint32_t { kOutF64 = 0, kOutF32 = 1, kOutBF16 = 2, kOutF16 = 3 };
+
+struct KernelCommon {
+  StreamHdr *hdr;
+  unsigned char *arena;
+  uint32_t *err;  // device fault word (bit 0: non-finite or zero sum of squares)
+  uint32_t n;     // pool size of every item of this launch
+  uint32_t R;     // passes per emitted pool
+  uint32_t K;     // renormalisation period (0 = never)
+  uint32_t chi2;  // chi-square mode
+  Chi2Consts cc;
+};
+
+struct SeedArgs {
+  KernelCommon c;
+  const uint32_t *streams;  // stream ids of this launch (all of pool size c.n)
+  uint32_t nstreams;
+  uint32_t warmup;  // warm-up passes
+  uint64_t seed;
+};
+
+struct FillArgs {
+  KernelCommon c;
+  const WorkItem *items;  // device array, or null for the affine form below
+  uint32_t nitems;
+  uint32_t affine_s0;     // affine form: item j = (s0 + j, count_each, j * count_each)
+  uint64_t count_each;
+  void *out;
+};
+
+// Launchers (wn_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_seed(const SeedArgs &a, bool pool_f64, hipStream_t s);
+hipError_t launch_fill(const FillArgs &a, bool pool_f64, uint32_t out_dtype, hipStream_t s);
+
+}  // namespace wn

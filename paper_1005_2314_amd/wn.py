@@ -1,0 +1,206 @@
+"""ctypes binding of the C ABI in ``include/wn.h`` (argument marshalling only).
+
+Every step of generation runs in the HIP kernels of ``libwn.so``.  PyTorch is
+used only for device memory (output tensors) and streams.  If the library is
+missing the binding raises; nothing falls back to a CPU path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwn.so")
+
+WN_OK, WN_EINVAL, WN_ENOMEM, WN_EDEVICE, WN_ESTATE, WN_ENOTSUP = range(6)
+WN_F64, WN_F32, WN_BF16, WN_F16 = range(4)
+WN_CHI2_CUBIC, WN_CHI2_OFF, WN_CHI2_FISHER, WN_CHI2_WH = range(4)
+STATUS_NAMES = {0: "WN_OK", 1: "WN_EINVAL", 2: "WN_ENOMEM", 3: "WN_EDEVICE", 4: "WN_ESTATE",
+                5: "WN_ENOTSUP"}
+
+# every symbol include/wn.h declares
+EXPORTED = ("wn_create", "wn_seed", "wn_fill", "wn_sync", "wn_get_stream", "wn_destroy",
+            "wn_last_error", "wn_version")
+
+
+class wn_config(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("num_streams", C.c_uint32),
+                ("pool_n", C.POINTER(C.c_uint32)), ("default_pool_n", C.c_uint32),
+                ("passes_per_output", C.c_uint32), ("pool_dtype", C.c_int),
+                ("chi2", C.c_int), ("renorm_period", C.c_uint32), ("device", C.c_int)]
+
+
+class wn_stream_info(C.Structure):
+    _fields_ = [("xs", C.c_uint64), ("k", C.c_uint64), ("n", C.c_uint32),
+                ("cursor", C.c_uint32), ("f", C.c_double), ("xnext", C.c_double),
+                ("qlast", C.c_double)]
+
+
+class WnError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libwn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.wn_create.argtypes = [C.POINTER(wn_config), C.POINTER(vp)]
+        L.wn_create.restype = C.c_int
+        L.wn_seed.argtypes = [vp, C.c_uint64, vp]
+        L.wn_seed.restype = C.c_int
+        L.wn_fill.argtypes = [vp, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64), vp,
+                              C.c_int, vp]
+        L.wn_fill.restype = C.c_int
+        L.wn_sync.argtypes = [vp]
+        L.wn_sync.restype = C.c_int
+        L.wn_get_stream.argtypes = [vp, C.c_uint32, C.POINTER(wn_stream_info), vp]
+        L.wn_get_stream.restype = C.c_int
+        L.wn_destroy.argtypes = [vp]
+        L.wn_destroy.restype = None
+        L.wn_last_error.argtypes = []
+        L.wn_last_error.restype = C.c_char_p
+        L.wn_version.argtypes = []
+        L.wn_version.restype = C.c_uint32
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return load().wn_last_error().decode()
+
+
+def check(status: int):
+    if status != WN_OK:
+        raise WnError(status, last_error())
+
+
+# ---- the C functions under their own names ------------------------------------
+
+def wn_create(cfg: wn_config):
+    h = C.c_void_p()
+    check(load().wn_create(C.byref(cfg), C.byref(h)))
+    return h
+
+
+def wn_seed(g, seed: int, stream=None):
+    check(load().wn_seed(g, seed, stream))
+
+
+def wn_fill(g, streams, counts, out_ptr, out_dtype: int, stream=None):
+    streams = np.ascontiguousarray(streams, np.uint32)
+    counts = np.ascontiguousarray(counts, np.uint64)
+    check(load().wn_fill(g, streams.size, streams.ctypes.data_as(C.POINTER(C.c_uint32)),
+                         counts.ctypes.data_as(C.POINTER(C.c_uint64)), out_ptr, out_dtype,
+                         stream))
+
+
+def wn_sync(g):
+    check(load().wn_sync(g))
+
+
+def wn_destroy(g):
+    load().wn_destroy(g)
+
+
+def make_config(num_streams, pool_n=4096, R=2, pool_dtype=WN_F32, chi2=WN_CHI2_CUBIC, K=16,
+                device=0):
+    cfg = wn_config()
+    cfg.struct_size = C.sizeof(wn_config)
+    cfg.num_streams = int(num_streams)
+    keep = None
+    if np.ndim(pool_n) > 0:
+        keep = np.ascontiguousarray(pool_n, np.uint32)
+        cfg.pool_n = keep.ctypes.data_as(C.POINTER(C.c_uint32))
+        cfg.default_pool_n = int(keep[0])
+    else:
+        cfg.pool_n = None
+        cfg.default_pool_n = int(pool_n)
+    cfg.passes_per_output = int(R)
+    cfg.pool_dtype = int(pool_dtype)
+    cfg.chi2 = int(chi2)
+    cfg.renorm_period = int(K)
+    cfg.device = int(device)
+    return cfg, keep
+
+
+_TORCH_DTYPES = None
+
+
+def torch_dtype(out_dtype):
+    import torch
+    return {WN_F64: torch.float64, WN_F32: torch.float32, WN_BF16: torch.bfloat16,
+            WN_F16: torch.float16}[out_dtype]
+
+
+class Generator:
+    """A set of independent streams on one GPU (owns a ``wn_gen``)."""
+
+    def __init__(self, num_streams, pool_n=4096, R=2, pool_dtype=WN_F32, chi2=WN_CHI2_CUBIC,
+                 K=16, device=0):
+        self.cfg, keep = make_config(num_streams, pool_n, R, pool_dtype, chi2, K, device)
+        self.num_streams = int(num_streams)
+        self.pool_f64 = pool_dtype == WN_F64
+        self.device = device
+        self._h = wn_create(self.cfg)
+        del keep  # the library copied the pool sizes
+
+    def close(self):
+        if getattr(self, "_h", None):
+            wn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _stream_handle(stream):
+        if stream is None:
+            import torch
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        if isinstance(stream, int):
+            return C.c_void_p(stream)
+        return C.c_void_p(stream.cuda_stream)
+
+    def seed(self, seed: int, stream=None):
+        wn_seed(self._h, seed, self._stream_handle(stream))
+
+    def fill_into(self, out, streams, counts, stream=None):
+        """Fill a caller-owned CUDA tensor (dtype selects the output type)."""
+        import torch
+        dt = {torch.float64: WN_F64, torch.float32: WN_F32, torch.bfloat16: WN_BF16,
+              torch.float16: WN_F16}[out.dtype]
+        total = int(np.sum(np.asarray(counts, np.uint64)))
+        if out.numel() < total or not out.is_contiguous() or not out.is_cuda:
+            raise ValueError("out must be a contiguous CUDA tensor with sum(counts) elements")
+        wn_fill(self._h, streams, counts, C.c_void_p(out.data_ptr()), dt,
+                self._stream_handle(stream))
+        return out
+
+    def fill(self, streams, counts, out_dtype=WN_F32, stream=None):
+        import torch
+        total = int(np.sum(np.asarray(counts, np.uint64)))
+        out = torch.empty(total, dtype=torch_dtype(out_dtype), device=f"cuda:{self.device}")
+        return self.fill_into(out, streams, counts, stream)
+
+    def sync(self):
+        wn_sync(self._h)
+
+    def stream_state(self, s: int):
+        info = wn_stream_info()
+        pool = None
+        check(load().wn_get_stream(self._h, s, C.byref(info), None))
+        pool = np.zeros(info.n, np.float64 if self.pool_f64 else np.float32)
+        check(load().wn_get_stream(self._h, s, C.byref(info), C.c_void_p(pool.ctypes.data)))
+        return info, pool

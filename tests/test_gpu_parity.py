@@ -1,0 +1,163 @@
+"""GPU parity: the HIP path against the CPU oracle, bit for bit.
+
+Binary32 outputs (and every other output type) must equal the oracle's bits,
+including signed zeros; so must the seeded state and the stream headers.  The
+integer path (uniform draws, gather maps) is covered by the same comparison:
+any difference in a draw or an index changes every later bit.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import Pair, assert_bits_equal, bits
+from paper_1005_2314_amd import wn as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    W.load()
+
+
+@pytest.mark.parametrize("pool", ["f32", "f64"])
+@pytest.mark.parametrize("n", [16, 64, 256, 1024, 2048, 4096, 16384])
+def test_seeded_state_matches(pool, n):
+    p = Pair(5, pool_n=n, R=2, pool=pool, seed=1234)
+    for s in (0, 3, 4):
+        gi, gp = p.gpu.stream_state(s)
+        oi, op = p.orc.stream(s)
+        assert_bits_equal(bits(gp), bits(op), f"pool n={n} s={s}")
+        assert (gi.xs, gi.k, gi.n, gi.cursor) == (oi.xs, oi.k, oi.n, oi.cursor)
+        assert bits(np.float64(gi.xnext)) == bits(np.float64(oi.xnext))
+        assert bits(np.float64(gi.qlast)) == bits(np.float64(oi.qlast))
+
+
+CASES = [
+    # n, R, pool, out, chi2, K
+    (16, 1, "f32", W.WN_F32, 0, 16),
+    (64, 2, "f32", W.WN_F32, 0, 4),
+    (512, 3, "f32", W.WN_F32, 0, 16),
+    (1024, 1, "f64", W.WN_F64, 0, 16),
+    (1024, 2, "f32", W.WN_F32, 0, 16),
+    (2048, 2, "f32", W.WN_BF16, 0, 16),
+    (4096, 2, "f32", W.WN_F32, 0, 3),
+    (4096, 2, "f32", W.WN_F16, 0, 16),
+    (4096, 2, "f64", W.WN_F32, 0, 16),
+    (4096, 2, "f64", W.WN_BF16, 0, 16),
+    (4096, 1, "f64", W.WN_F16, 0, 16),
+    (8192, 2, "f32", W.WN_F32, 0, 16),
+    (16384, 1, "f32", W.WN_F32, 0, 16),
+    (16384, 1, "f64", W.WN_F64, 0, 16),
+    (1024, 2, "f32", W.WN_F32, 1, 16),   # rescale off
+    (1024, 2, "f32", W.WN_F32, 2, 16),   # Fisher
+    (1024, 2, "f64", W.WN_F64, 3, 0),    # Wilson-Hilferty, no renormalisation
+]
+
+
+@pytest.mark.parametrize("n,R,pool,out,chi2,K", CASES)
+def test_fill_bit_exact(n, R, pool, out, chi2, K):
+    ns = 6
+    p = Pair(ns, pool_n=n, R=R, pool=pool, chi2=chi2, K=K, seed=99)
+    per = 5 * (n - 1) + 17  # several pools and a ragged tail
+    g, o = p.fill(np.arange(ns), [per] * ns, out)
+    assert_bits_equal(g, o, "first call")
+    # continue: odd counts, crossing pool boundaries, a zero count, shuffled order
+    streams = [4, 0, 5, 2, 1, 3]
+    counts = [1, n - 1, 0, 2 * n + 3, 7, 3 * (n - 1) - 17]
+    g, o = p.fill(streams, counts, out)
+    assert_bits_equal(g, o, "second call")
+
+
+def test_split_calls_equal_one_call():
+    n = 1024
+    a = Pair(3, pool_n=n, R=2, seed=5)
+    b = Pair(3, pool_n=n, R=2, seed=5)
+    whole, _ = a.fill([0, 1, 2], [10000, 10000, 10000])
+    parts = []
+    for c in (1, 1022, 1023, 5000, 2954):
+        g, o = b.fill([0, 1, 2], [c, c, c])
+        assert_bits_equal(g, o, f"part {c}")
+        parts.append(g.reshape(3, c))
+    got = np.concatenate(parts, axis=1).reshape(-1)
+    assert_bits_equal(got, whole, "split vs whole")
+
+
+def test_mixed_pool_sizes_work_list():
+    sizes = np.array([1024, 2048, 4096, 64, 1024, 16384, 2048, 4096], np.uint32)
+    p = Pair(len(sizes), pool_n=sizes, R=2, seed=77)
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        order = rng.permutation(len(sizes))
+        counts = rng.integers(0, 30000, size=len(sizes))
+        g, o = p.fill(order, counts)
+        assert_bits_equal(g, o, "mixed")
+
+
+def test_many_streams_small_requests():
+    p = Pair(3000, pool_n=1024, R=2, seed=3)
+    counts = np.random.default_rng(2).integers(0, 3000, size=3000)
+    g, o = p.fill(np.arange(3000), counts)
+    assert_bits_equal(g, o, "3000 streams")
+
+
+def test_plain_f64_form_full_size():
+    """One stream, pool 1024 binary64, R = 1, 2^20 binary64 outputs."""
+    p = Pair(1, pool_n=1024, R=1, pool="f64", seed=1)
+    g, o = p.fill([0], [1 << 20], W.WN_F64)
+    assert_bits_equal(g, o, "plain f64")
+
+
+def test_batched_f32_full_size_sampled():
+    """65536 streams x 2^14 (2^30 binary32 values), checked on sampled streams,
+    in the launch shape the benchmark times."""
+    from paper_1005_2314_amd import inputs
+    w = inputs.batched_f32()
+    p = Pair(w["num_streams"], pool_n=w["pool_n"], R=w["R"], seed=w["seed"])
+    sample = inputs.sample_streams(w["num_streams"], 8)
+    for call in range(2):
+        g, o = p.fill(w["streams"], w["counts"], W.WN_F32, orc_streams=sample)
+        assert_bits_equal(g, o, f"call {call}")
+
+
+def test_errors_leave_state_unchanged():
+    p = Pair(4, pool_n=256, R=2, seed=8)
+    import torch
+    out = torch.empty(100, device="cuda")
+    with pytest.raises(W.WnError) as ei:
+        p.gpu.fill_into(out, [1, 1], [10, 10])
+    assert ei.value.status == W.WN_EINVAL
+    with pytest.raises(W.WnError) as ei:
+        p.gpu.fill_into(out, [4], [10])
+    assert ei.value.status == W.WN_EINVAL
+    with pytest.raises(W.WnError) as ei:
+        p.gpu.fill([0], [10], W.WN_F64)
+    assert ei.value.status == W.WN_ENOTSUP
+    g, o = p.fill([0, 1, 2, 3], [300, 300, 300, 300])
+    assert_bits_equal(g, o, "after errors")
+    p.gpu.sync()
+
+
+def test_fill_before_seed_is_estate():
+    g = W.Generator(2, pool_n=64, R=1)
+    with pytest.raises(W.WnError) as ei:
+        g.fill([0], [10])
+    assert ei.value.status == W.WN_ESTATE
+
+
+def test_two_streams_ordering():
+    """Calls on different HIP streams are ordered by the generator's event."""
+    import torch
+    p = Pair(2, pool_n=1024, R=2, seed=21)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(s1):
+        a = p.gpu.fill([0, 1], [5000, 5000], stream=s1)
+    with torch.cuda.stream(s2):
+        b = p.gpu.fill([0, 1], [5000, 5000], stream=s2)
+    torch.cuda.synchronize()
+    from gpu_util import to_numpy_bits
+    oa = bits(p.orc.fill([0, 1], [5000, 5000]))
+    ob = bits(p.orc.fill([0, 1], [5000, 5000]))
+    assert_bits_equal(to_numpy_bits(a), oa, "first stream")
+    assert_bits_equal(to_numpy_bits(b), ob, "second stream")
