@@ -27,9 +27,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="wall time of the timed oracle baseline calls")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparators", action="store_true")
     return ap.parse_args()
 
 
@@ -43,9 +44,10 @@ def workload_bytes(w, out_bytes_per_value):
 
 
 def cpu_baseline(w, target_seconds):
-    """The oracle, untuned, on all host cores, over a bounded sample of streams:
-    one untimed call (it seeds the sampled streams), then one timed call of the
-    same per-stream count, as the GPU steps continue their streams."""
+    """The oracle, untuned, on all host cores (OpenMP over streams), over a bounded
+    sample of the workload's streams: one untimed call seeds them, then continuing
+    calls of the same per-stream count are timed until `target_seconds` of wall
+    time have passed, as the GPU steps continue their streams."""
     import numpy as np
 
     from oracle import oracle as O
@@ -59,19 +61,82 @@ def cpu_baseline(w, target_seconds):
     probe.fill(np.arange(m), [per] * m)
     rate = m * per / (time.perf_counter() - t0)
     del probe
-    k = int(max(threads, min(w["num_streams"], rate * target_seconds / per)))
-    k = max(threads, (k // threads) * threads)
+    # at most the whole workload, at least one call of about a second
+    k = int(min(w["num_streams"], max(m, rate * 1.0 / per)))
     g = O.Generator(w["num_streams"], pool_n=w["pool_n"], R=w["R"], pool_dtype="f32")
     g.seed(w["seed"])
     streams = np.arange(k, dtype=np.uint32)
     g.fill(streams, [per] * k)
+    calls = 0
     t0 = time.perf_counter()
-    g.fill(streams, [per] * k)
-    dt = time.perf_counter() - t0
-    return {"value": k * per / dt, "unit": "normals/s", "cores": threads, "kind": "oracle",
-            "sample": f"streams 0..{k - 1} of {w['num_streams']} (pool 4096 f32, R=2), "
-                      f"one continuing call of {per} values each after an untimed call; "
-                      f"{dt:.1f} s"}
+    while True:
+        g.fill(streams, [per] * k)
+        calls += 1
+        dt = time.perf_counter() - t0
+        if dt >= target_seconds:
+            break
+    return {"value": calls * k * per / dt, "unit": "normals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"streams 0..{k - 1} of {w['num_streams']} (pool 4096 f32, R=2): "
+                      f"{calls} continuing calls of {per} values per stream after an untimed "
+                      f"seeding call, {dt:.1f} s wall on {threads} threads"}
+
+
+def time_launch(fn, stream, reps=3, warmup=1):
+    """Median duration (ms) of fn() enqueued on `stream`, by HIP events on that stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return sorted(ts)[len(ts) // 2]
+
+
+def comparators(W, w, out, stream):
+    """Reference points on the same GPU: HBM write ceiling, the generator's traffic
+    with no arithmetic, the plain single-stream binary64 form, Box-Muller."""
+    import ctypes as C
+
+    import torch
+
+    from paper_1005_2314_amd import inputs
+    res = {}
+    total = out.numel()
+    st = C.c_void_p(stream.cuda_stream)
+    optr = C.c_void_p(out.data_ptr())
+    for width in (1, 4):
+        ms = time_launch(lambda: W.wn_bench_store(optr, total * 4, width, st), stream)
+        res[f"store_ceiling_dwordx{width}"] = {"ms": ms, "GB_per_s": total * 4 / ms / 1e6}
+    n = w["pool_n"]
+    state = torch.zeros(w["num_streams"] * (n * 4 + 64), dtype=torch.uint8, device=out.device)
+    sptr = C.c_void_p(state.data_ptr())
+    ms = time_launch(lambda: W.wn_bench_traffic(sptr, optr, w["num_streams"], n,
+                                                int(w["counts"][0]), st), stream)
+    out_b, state_b = workload_bytes(w, 4)
+    res["traffic_ceiling"] = {"ms": ms, "GB_per_s": (out_b + state_b) / ms / 1e6,
+                              "normals_per_s": total / ms * 1e3,
+                              "what": "the fill's HBM traffic with no arithmetic"}
+    del state
+    for fast in (0, 1):
+        ms = time_launch(lambda: W.wn_bench_box_muller(optr, total, W.WN_F32, 1, fast, st), stream)
+        res["box_muller_philox_f32" + ("_fast" if fast else "")] = {
+            "ms": ms, "normals_per_s": total / ms * 1e3, "GB_per_s": total * 4 / ms / 1e6}
+    p = inputs.plain_f64()
+    g = W.Generator(1, pool_n=p["pool_n"], R=p["R"], pool_dtype=W.WN_F64)
+    g.seed(p["seed"])
+    o64 = torch.empty(int(p["counts"][0]), dtype=torch.float64, device=out.device)
+    ms = time_launch(lambda: g.fill_into(o64, p["streams"], p["counts"], stream), stream)
+    res["plain_f64_single_stream"] = {"ms": ms, "normals_per_s": o64.numel() / ms * 1e3,
+                                      "what": "1 stream, pool 1024 binary64, R=1, 2^20 binary64"}
+    g.close()
+    return res
 
 
 def main():
@@ -148,6 +213,8 @@ def main():
                      "state_bytes": state_b,
                      "output_write_frac": out_b / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
+    if not args.no_comparators:
+        rec["comparators"] = comparators(W, w, out, stream)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

@@ -76,6 +76,15 @@ typedef struct {
   double qlast;    /* binary64 sum of squares of the current pool */
 } wn_stream_info;
 
+/* Launch choices that never change results (bit-exact across all settings);
+ * an autotuner may pick them per workload. */
+typedef struct {
+  uint32_t struct_size;        /* sizeof(wn_tuning) */
+  uint32_t lds_double_buffer;  /* 1: two LDS pool buffers, one barrier per pass */
+  uint32_t nontemporal_stores; /* 1: output stores bypass cache retention */
+  uint32_t high_occupancy;     /* 1: cap registers for 8 waves per SIMD (not with nontemporal) */
+} wn_tuning;
+
 /* Validate cfg, select the device, allocate the per-stream state in device
  * memory (pools and 64-byte headers) and compute the chi-square constants on
  * the host.  *out_gen receives the generator (NULL on failure).
@@ -108,6 +117,14 @@ wn_status wn_sync(wn_gen *g);
 /* Copy stream s's state to the host (synchronous).  pool_out (nullable)
  * receives n values of the pool type. */
 wn_status wn_get_stream(wn_gen *g, uint32_t s, wn_stream_info *info, void *pool_out);
+
+/* Set or read the generator's launch choices.  wn_set_tuning validates the
+ * struct (WN_EINVAL on a bad size, a flag other than 0/1, or high_occupancy
+ * with nontemporal_stores) and applies to later calls.  Binary32 pools of
+ * 1024..8192 values have every choice; other shapes ignore them.  Defaults:
+ * the choices measured fastest for binary32 pools on MI355X. */
+wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t);
+wn_status wn_get_tuning(wn_gen *g, wn_tuning *t);
 
 /* Free everything the generator owns.  NULL-safe.  Waits for its work. */
 void wn_destroy(wn_gen *g);

@@ -12,8 +12,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwn.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("wn_kernels.hip", "wn_api.cpp")]
-HEADERS = [os.path.join(CSRC, "wn_internal.hpp"), os.path.join(ROOT, "include", "wn.h")]
+SOURCES = [os.path.join(CSRC, f) for f in ("wn_kernels.hip", "wn_bench.hip", "wn_api.cpp")]
+HEADERS = [os.path.join(CSRC, "wn_internal.hpp"), os.path.join(ROOT, "include", "wn.h"),
+           os.path.join(ROOT, "include", "wn_bench.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -100,6 +100,7 @@ struct wn_gen {
   ListSlot slots[4];
   unsigned next_slot = 0;
   std::vector<uint8_t> seen;  // duplicate check scratch
+  uint32_t variant = 1;       // non-semantic kernel variant (wn_tuning); LDS double buffer
 };
 
 namespace {
@@ -365,6 +366,7 @@ wn_status wn_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint6
     a.affine_s0 = streams[0];
     a.count_each = counts[0];
     a.out = out;
+    a.variant = g->variant;
     if ((e = wn::launch_fill(a, g->pool_f64, uint32_t(out_dtype), st)) != hipSuccess)
       return hip_fail(e, "wn_fill: launch");
     if ((e = record_last(g, st)) != hipSuccess) return hip_fail(e, "wn_fill: event");
@@ -427,6 +429,7 @@ wn_status wn_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint6
     a.affine_s0 = 0;
     a.count_each = 0;
     a.out = out;
+    a.variant = g->variant;
     if ((e = wn::launch_fill(a, g->pool_f64, uint32_t(out_dtype), st)) != hipSuccess)
       return hip_fail(e, "wn_fill: launch");
   }
@@ -473,6 +476,28 @@ wn_status wn_get_stream(wn_gen *g, uint32_t s, wn_stream_info *info, void *pool_
                      size_t(g->pool_n[s]) * (g->pool_f64 ? 8 : 4), hipMemcpyDeviceToHost)) !=
           hipSuccess)
     return hip_fail(e, "wn_get_stream: pool");
+  return WN_OK;
+}
+
+wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t) {
+  if (!g || !t) return fail(WN_EINVAL, "wn_set_tuning: NULL argument");
+  if (t->struct_size != sizeof(wn_tuning))
+    return fail(WN_EINVAL, "wn_set_tuning: struct_size %u, expected %zu", t->struct_size,
+                sizeof(wn_tuning));
+  if (t->lds_double_buffer > 1 || t->nontemporal_stores > 1 || t->high_occupancy > 1 ||
+      (t->high_occupancy && t->nontemporal_stores))
+    return fail(WN_EINVAL, "wn_set_tuning: flags must be 0 or 1 (high_occupancy without "
+                           "nontemporal_stores)");
+  g->variant = t->lds_double_buffer | (t->nontemporal_stores << 1) | (t->high_occupancy << 2);
+  return WN_OK;
+}
+
+wn_status wn_get_tuning(wn_gen *g, wn_tuning *t) {
+  if (!g || !t) return fail(WN_EINVAL, "wn_get_tuning: NULL argument");
+  t->struct_size = sizeof(wn_tuning);
+  t->lds_double_buffer = g->variant & 1u;
+  t->nontemporal_stores = (g->variant >> 1) & 1u;
+  t->high_occupancy = (g->variant >> 2) & 1u;
   return WN_OK;
 }
 

@@ -64,6 +64,7 @@ struct FillArgs {
   uint32_t affine_s0;     // affine form: item j = (s0 + j, count_each, j * count_each)
   uint64_t count_each;
   void *out;
+  uint32_t variant;       // non-semantic kernel variant (bit 0: LDS double buffer, bit 1: NT stores)
 };
 
 // Launchers (wn_kernels.hip).  Return hipSuccess or the launch error.

@@ -173,14 +173,17 @@ struct Cast<Half> {
 
 // ---- the per-workgroup pool engine ------------------------------------------------
 // SMALL: pools with L < 256, launched with BD = L threads and NQ = 1.
+// DB: two LDS pool buffers; a pass reads one and writes the other, so it needs
+// one barrier instead of two (twice the LDS).
 //
 // Barrier discipline: every LDS pool write is followed by a barrier before the
 // pool is read again; sumsq() ends with a barrier that also publishes the pool
 // writes before it.  Two sumsq() calls must be separated by a barrier (the
 // second one rewrites the partial-sum slots the first one's readers use).
-template <typename T, int NQ, bool SMALL>
+template <typename T, int NQ, bool SMALL, bool DB>
 struct Engine {
-  T *P;         // LDS pool, n elements
+  T *cur;       // LDS buffer holding the pool
+  T *nxt;       // LDS buffer the next pass writes (== cur unless DB)
   double *red;  // LDS, 4 partial sums
   uint32_t L;
   uint32_t tid;
@@ -199,7 +202,7 @@ struct Engine {
       for (int c = 0; c < NQ; ++c) {
         const T v = g[pos(m, c)];
         y[c][m] = v;
-        P[pos(m, c)] = v;
+        cur[pos(m, c)] = v;
       }
   }
 
@@ -207,7 +210,7 @@ struct Engine {
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int c = 0; c < NQ; ++c) y[c][m] = P[pos(m, c)];
+      for (int c = 0; c < NQ; ++c) y[c][m] = cur[pos(m, c)];
   }
 
   __device__ __forceinline__ void store_global(T *__restrict__ g) const {
@@ -217,11 +220,12 @@ struct Engine {
       for (int c = 0; c < NQ; ++c) g[pos(m, c)] = y[c][m];
   }
 
+  // write the registers to the buffer holding the pool
   __device__ __forceinline__ void write_lds() {
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int c = 0; c < NQ; ++c) P[pos(m, c)] = y[c][m];
+      for (int c = 0; c < NQ; ++c) cur[pos(m, c)] = y[c][m];
   }
 
   // y <- T(double(y) * g)
@@ -242,7 +246,7 @@ struct Engine {
       const uint32_t step = a * bd();
 #pragma unroll
       for (int c = 0; c < NQ; ++c)
-        x[c][m] = P[uint32_t(m) * L + ((base + step * uint32_t(c)) & (L - 1))];
+        x[c][m] = cur[uint32_t(m) * L + ((base + step * uint32_t(c)) & (L - 1))];
     }
     if (renorm) {
 #pragma unroll
@@ -254,7 +258,7 @@ struct Engine {
     for (int c = 0; c < NQ; ++c) quad<K>(x[c][0], x[c][1], x[c][2], x[c][3], y[c]);
   }
 
-  // One pass: gather from the LDS pool, transform, barrier, write back.  The
+  // One pass: gather from the LDS pool, transform, write the new pool.  The
   // caller places a barrier before the next read of the pool.  `renorm`
   // applies the renormalisation scale g to every gathered value first (each
   // element is gathered exactly once per pass, so this equals rescaling the
@@ -266,8 +270,16 @@ struct Engine {
       case 2: gather_transform<2>(p, renorm, g); break;
       default: gather_transform<3>(p, renorm, g); break;
     }
-    __syncthreads();
-    write_lds();
+    if (!DB) __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) nxt[pos(m, c)] = y[c][m];
+    if (DB) {
+      T *t = cur;
+      cur = nxt;
+      nxt = t;
+    }
   }
 
   // Sum of squares of the pool held in y: running sum over this thread's
@@ -290,25 +302,50 @@ struct Engine {
     return acc;
   }
 
+  template <bool NT, typename O>
+  __device__ __forceinline__ static void put(O *p, O v) {
+    if constexpr (!NT) {
+      *p = v;
+    } else if constexpr (sizeof(O) == 2) {
+      __builtin_nontemporal_store(v.u, &p->u);
+    } else {
+      __builtin_nontemporal_store(v, p);
+    }
+  }
+
   // Emit pool positions [lo, hi) scaled by fT to out[obase + (i - lo)].
-  template <typename O>
+  template <bool NT, typename O>
   __device__ __forceinline__ void emit(O *__restrict__ out, uint64_t obase, uint32_t lo,
                                        uint32_t hi, T fT) const {
+    if (lo == 0 && hi == 4 * L - 1) {
+      // a whole pool: every position but the withheld last one
+      O *dst = out + obase + tid;
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) {
+          const O v = Cast<O>::from(T(y[c][m] * fT));
+          if (m < 3 || c < NQ - 1 || tid < bd() - 1)
+            put<NT>(dst + (uint32_t(m) * L + uint32_t(c) * bd()), v);
+        }
+      return;
+    }
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
       for (int c = 0; c < NQ; ++c) {
         const uint32_t i = pos(m, c);
-        if (i >= lo && i < hi) out[obase + (i - lo)] = Cast<O>::from(T(y[c][m] * fT));
+        if (i >= lo && i < hi) put<NT>(out + (obase + (i - lo)), Cast<O>::from(T(y[c][m] * fT)));
       }
   }
 };
 
-template <typename T, int NQ, bool SMALL>
-__device__ __forceinline__ Engine<T, NQ, SMALL> make_engine(unsigned char *smem, uint32_t n) {
-  Engine<T, NQ, SMALL> e;
-  e.P = reinterpret_cast<T *>(smem);
-  e.red = reinterpret_cast<double *>(smem + size_t(n) * sizeof(T));
+template <typename T, int NQ, bool SMALL, bool DB>
+__device__ __forceinline__ Engine<T, NQ, SMALL, DB> make_engine(unsigned char *smem, uint32_t n) {
+  Engine<T, NQ, SMALL, DB> e;
+  e.cur = reinterpret_cast<T *>(smem);
+  e.nxt = DB ? e.cur + n : e.cur;
+  e.red = reinterpret_cast<double *>(smem + size_t(n) * sizeof(T) * (DB ? 2 : 1));
   e.L = n / 4;
   e.tid = threadIdx.x;
   return e;
@@ -325,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
   __shared__ uint64_t xs_shared;
   const uint32_t s = a.streams[blockIdx.x];
   const uint32_t n = a.c.n;
-  auto e = make_engine<T, NQ, SMALL>(smem, n);
+  auto e = make_engine<T, NQ, SMALL, false>(smem, n);
   StreamHdr *h = a.c.hdr + s;
 
   // Initial values from the top 23 bits of successive uniforms:
@@ -335,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
     for (uint32_t i = 0; i < n; ++i) {
       const uint64_t v = xs_next(xs);
       const double c = __dadd_rn(double(int64_t(v >> 41) - (int64_t(1) << 22)), 0.5);
-      e.P[i] = T(__dmul_rn(c, 0x1p-22));
+      e.cur[i] = T(__dmul_rn(c, 0x1p-22));
     }
     xs_shared = xs;
   }
@@ -360,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
   __syncthreads();
   Q = e.sumsq();
   if (e.tid == 0) flag_fault(a.c.err, Q);
-  const double last = double(e.P[n - 1]);
+  const double last = double(e.cur[n - 1]);
 
   e.store_global(reinterpret_cast<T *>(a.c.arena + h->pool_off));
   if (e.tid == 0) {
@@ -382,8 +419,8 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
 // f = sqrt(S / Q); the n-1 first positions are emitted as T(P[i] * T(f)) and
 // the withheld value f * P[n-1] feeds the next sample.  The stored pool is
 // never scaled.
-template <typename T, typename O, int NQ, bool SMALL>
-__global__ __launch_bounds__(kBlock) void k_fill(FillArgs a) {
+template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE>
+__global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t j = blockIdx.x;
   uint32_t s;
@@ -401,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(FillArgs a) {
   if (count == 0) return;
 
   const uint32_t n = a.c.n;
-  auto e = make_engine<T, NQ, SMALL>(smem, n);
+  auto e = make_engine<T, NQ, SMALL, DB>(smem, n);
   StreamHdr *h = a.c.hdr + s;
   uint64_t xs = h->xs;
   uint64_t k = h->k;
@@ -417,7 +454,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(FillArgs a) {
 
   if (cursor < n - 1) {
     const uint32_t take = count < uint64_t(n - 1 - cursor) ? uint32_t(count) : n - 1 - cursor;
-    e.template emit<O>(out, obase, cursor, cursor + take, T(f));
+    e.template emit<NT>(out, obase, cursor, cursor + take, T(f));
     obase += take;
     count -= take;
     cursor += take;
@@ -434,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(FillArgs a) {
       if (r + 1 < a.c.R) __syncthreads();
     }
     const double Q = e.sumsq();
-    const double last = double(e.P[n - 1]);
+    const double last = double(e.cur[n - 1]);
     double fk = 1.0;
     if (a.c.chi2 != kChi2Off) fk = __dsqrt_rn(__ddiv_rn(chi2_sample(a.c.cc, a.c.chi2, xnext), Q));
     if (e.tid == 0) flag_fault(a.c.err, Q);
@@ -443,7 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(FillArgs a) {
     qlast = Q;
     k += 1;
     const uint32_t take = count < uint64_t(n - 1) ? uint32_t(count) : n - 1;
-    e.template emit<O>(out, obase, 0, take, T(f));
+    e.template emit<NT>(out, obase, 0, take, T(f));
     obase += take;
     count -= take;
     cursor = take;
@@ -461,8 +498,8 @@ __global__ __launch_bounds__(kBlock) void k_fill(FillArgs a) {
 }
 
 // ---- dispatch ------------------------------------------------------------------------
-size_t lds_bytes(uint32_t n, bool pool_f64) {
-  return size_t(n) * (pool_f64 ? 8 : 4) + 4 * sizeof(double);
+size_t lds_bytes(uint32_t n, bool pool_f64, bool db) {
+  return size_t(n) * (pool_f64 ? 8 : 4) * (db ? 2 : 1) + 4 * sizeof(double);
 }
 
 template <typename Kern>
@@ -475,7 +512,7 @@ hipError_t prepare(Kern kern, size_t lds) {
 
 template <typename T, int NQ, bool SMALL>
 hipError_t seed_t(const SeedArgs &a, hipStream_t st) {
-  const size_t lds = lds_bytes(a.c.n, sizeof(T) == 8);
+  const size_t lds = lds_bytes(a.c.n, sizeof(T) == 8, false);
   auto kern = k_seed<T, NQ, SMALL>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
@@ -484,15 +521,33 @@ hipError_t seed_t(const SeedArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename T, typename O, int NQ, bool SMALL>
+template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE = 1>
 hipError_t fill_t(const FillArgs &a, hipStream_t st) {
-  const size_t lds = lds_bytes(a.c.n, sizeof(T) == 8);
-  auto kern = k_fill<T, O, NQ, SMALL>;
+  const size_t lds = lds_bytes(a.c.n, sizeof(T) == 8, DB);
+  auto kern = k_fill<T, O, NQ, SMALL, DB, NT, WPE>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
   const uint32_t block = SMALL ? a.c.n / 4 : kBlock;
   hipLaunchKernelGGL(kern, dim3(a.nitems), dim3(block), lds, st, a);
   return hipGetLastError();
+}
+
+// Non-semantic variants (identical results): bit 0 double-buffered LDS,
+// bit 1 nontemporal output stores, bit 2 at most 64 VGPRs (8 waves per SIMD).  Binary32 pools of 1024..8192 values have
+// all four; every other shape runs variant 0.
+template <typename T, typename O, int NQ>
+hipError_t fill_v(const FillArgs &a, hipStream_t st) {
+  if constexpr (sizeof(T) == 4 && NQ <= 8) {
+    switch (a.variant & 7u) {
+      case 1: return fill_t<T, O, NQ, false, true, false>(a, st);
+      case 2: return fill_t<T, O, NQ, false, false, true>(a, st);
+      case 3: return fill_t<T, O, NQ, false, true, true>(a, st);
+      case 4: return fill_t<T, O, NQ, false, false, false, 8>(a, st);
+      case 5: return fill_t<T, O, NQ, false, true, false, 8>(a, st);
+      default: break;
+    }
+  }
+  return fill_t<T, O, NQ, false, false, false>(a, st);
 }
 
 template <typename T>
@@ -510,12 +565,12 @@ hipError_t seed_n(const SeedArgs &a, hipStream_t st) {
 template <typename T, typename O>
 hipError_t fill_n(const FillArgs &a, hipStream_t st) {
   switch (a.c.n) {
-    case 1024: return fill_t<T, O, 1, false>(a, st);
-    case 2048: return fill_t<T, O, 2, false>(a, st);
-    case 4096: return fill_t<T, O, 4, false>(a, st);
-    case 8192: return fill_t<T, O, 8, false>(a, st);
-    case 16384: return fill_t<T, O, 16, false>(a, st);
-    default: return fill_t<T, O, 1, true>(a, st);
+    case 1024: return fill_v<T, O, 1>(a, st);
+    case 2048: return fill_v<T, O, 2>(a, st);
+    case 4096: return fill_v<T, O, 4>(a, st);
+    case 8192: return fill_v<T, O, 8>(a, st);
+    case 16384: return fill_v<T, O, 16>(a, st);
+    default: return fill_t<T, O, 1, true, false, false>(a, st);
   }
 }
 

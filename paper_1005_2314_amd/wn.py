@@ -18,9 +18,10 @@ WN_CHI2_CUBIC, WN_CHI2_OFF, WN_CHI2_FISHER, WN_CHI2_WH = range(4)
 STATUS_NAMES = {0: "WN_OK", 1: "WN_EINVAL", 2: "WN_ENOMEM", 3: "WN_EDEVICE", 4: "WN_ESTATE",
                 5: "WN_ENOTSUP"}
 
-# every symbol include/wn.h declares
+# every symbol include/wn.h and include/wn_bench.h declare
 EXPORTED = ("wn_create", "wn_seed", "wn_fill", "wn_sync", "wn_get_stream", "wn_destroy",
-            "wn_last_error", "wn_version")
+            "wn_last_error", "wn_version", "wn_set_tuning", "wn_get_tuning", "wn_bench_store", "wn_bench_traffic",
+            "wn_bench_box_muller")
 
 
 class wn_config(C.Structure):
@@ -34,6 +35,11 @@ class wn_stream_info(C.Structure):
     _fields_ = [("xs", C.c_uint64), ("k", C.c_uint64), ("n", C.c_uint32),
                 ("cursor", C.c_uint32), ("f", C.c_double), ("xnext", C.c_double),
                 ("qlast", C.c_double)]
+
+
+class wn_tuning(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("lds_double_buffer", C.c_uint32),
+                ("nontemporal_stores", C.c_uint32), ("high_occupancy", C.c_uint32)]
 
 
 class WnError(RuntimeError):
@@ -70,6 +76,16 @@ def load():
         L.wn_last_error.restype = C.c_char_p
         L.wn_version.argtypes = []
         L.wn_version.restype = C.c_uint32
+        L.wn_set_tuning.argtypes = [vp, C.POINTER(wn_tuning)]
+        L.wn_set_tuning.restype = C.c_int
+        L.wn_get_tuning.argtypes = [vp, C.POINTER(wn_tuning)]
+        L.wn_get_tuning.restype = C.c_int
+        L.wn_bench_store.argtypes = [vp, C.c_uint64, C.c_uint32, vp]
+        L.wn_bench_store.restype = C.c_int
+        L.wn_bench_traffic.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.c_uint64, vp]
+        L.wn_bench_traffic.restype = C.c_int
+        L.wn_bench_box_muller.argtypes = [vp, C.c_uint64, C.c_int, C.c_uint64, C.c_int, vp]
+        L.wn_bench_box_muller.restype = C.c_int
         _lib = L
     return _lib
 
@@ -109,6 +125,24 @@ def wn_sync(g):
 
 def wn_destroy(g):
     load().wn_destroy(g)
+
+
+def wn_bench_store(dst_ptr, nbytes, width, stream=None):
+    st = load().wn_bench_store(dst_ptr, nbytes, width, stream)
+    if st != WN_OK:
+        raise WnError(st, "wn_bench_store rejected its arguments")
+
+
+def wn_bench_traffic(state_ptr, out_ptr, num_streams, pool_n, per_stream, stream=None):
+    st = load().wn_bench_traffic(state_ptr, out_ptr, num_streams, pool_n, per_stream, stream)
+    if st != WN_OK:
+        raise WnError(st, "wn_bench_traffic rejected its arguments")
+
+
+def wn_bench_box_muller(out_ptr, count, out_dtype, seed, fast=False, stream=None):
+    st = load().wn_bench_box_muller(out_ptr, count, out_dtype, seed, int(bool(fast)), stream)
+    if st != WN_OK:
+        raise WnError(st, "wn_bench_box_muller rejected its arguments")
 
 
 def make_config(num_streams, pool_n=4096, R=2, pool_dtype=WN_F32, chi2=WN_CHI2_CUBIC, K=16,
@@ -196,6 +230,21 @@ class Generator:
 
     def sync(self):
         wn_sync(self._h)
+
+    def set_tuning(self, lds_double_buffer=None, nontemporal_stores=None, high_occupancy=None):
+        t = self.tuning()
+        if lds_double_buffer is not None:
+            t.lds_double_buffer = int(lds_double_buffer)
+        if nontemporal_stores is not None:
+            t.nontemporal_stores = int(nontemporal_stores)
+        if high_occupancy is not None:
+            t.high_occupancy = int(high_occupancy)
+        check(load().wn_set_tuning(self._h, C.byref(t)))
+
+    def tuning(self):
+        t = wn_tuning()
+        check(load().wn_get_tuning(self._h, C.byref(t)))
+        return t
 
     def stream_state(self, s: int):
         info = wn_stream_info()

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "wn.h")).read()
+    text = "".join(open(os.path.join(ROOT, "include", h)).read() for h in ("wn.h", "wn_bench.h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(wn_[a-z_]+)\s*\(", text)))
 

@@ -161,3 +161,28 @@ def test_two_streams_ordering():
     ob = bits(p.orc.fill([0, 1], [5000, 5000]))
     assert_bits_equal(to_numpy_bits(a), oa, "first stream")
     assert_bits_equal(to_numpy_bits(b), ob, "second stream")
+
+
+@pytest.mark.parametrize("db,nt,oc", [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1),
+                                      (1, 0, 1)])
+@pytest.mark.parametrize("n,out", [(1024, W.WN_F32), (2048, W.WN_BF16), (4096, W.WN_F32),
+                                   (4096, W.WN_F16), (8192, W.WN_F32)])
+def test_tuning_variants_bit_exact(db, nt, oc, n, out):
+    ns = 5
+    p = Pair(ns, pool_n=n, R=2, seed=31, K=3)
+    p.gpu.set_tuning(lds_double_buffer=db, nontemporal_stores=nt, high_occupancy=oc)
+    t = p.gpu.tuning()
+    assert (t.lds_double_buffer, t.nontemporal_stores, t.high_occupancy) == (db, nt, oc)
+    g, o = p.fill(np.arange(ns), [4 * (n - 1) + 5] * ns, out)
+    assert_bits_equal(g, o, "affine")
+    g, o = p.fill([3, 1, 4], [n + 7, 2 * n, 1], out)
+    assert_bits_equal(g, o, "work list")
+
+
+def test_tuning_rejects_bad_values():
+    g = W.Generator(2, pool_n=64, R=1)
+    t = g.tuning()
+    t.lds_double_buffer = 2
+    with pytest.raises(W.WnError) as ei:
+        W.check(W.load().wn_set_tuning(g._h, W.C.byref(t)))
+    assert ei.value.status == W.WN_EINVAL
