@@ -82,7 +82,11 @@ typedef struct {
   uint32_t struct_size;        /* sizeof(wn_tuning) */
   uint32_t lds_double_buffer;  /* 1: two LDS pool buffers, one barrier per pass */
   uint32_t nontemporal_stores; /* 1: output stores bypass cache retention */
-  uint32_t high_occupancy;     /* 1: cap registers for 8 waves per SIMD (not with nontemporal) */
+  uint32_t high_occupancy;     /* 1: cap registers for 8 waves per SIMD (not with nontemporal;
+                                  one-size launches only) */
+  uint32_t wgs_per_cu;         /* persistent launches: workgroups per compute unit
+                                  (0 = as many as can be resident), <= 16 */
+  uint32_t use_graph;          /* 1: persistent launches replay a captured HIP graph */
 } wn_tuning;
 
 /* Validate cfg, select the device, allocate the per-stream state in device
@@ -119,12 +123,23 @@ wn_status wn_sync(wn_gen *g);
 wn_status wn_get_stream(wn_gen *g, uint32_t s, wn_stream_info *info, void *pool_out);
 
 /* Set or read the generator's launch choices.  wn_set_tuning validates the
- * struct (WN_EINVAL on a bad size, a flag other than 0/1, or high_occupancy
- * with nontemporal_stores) and applies to later calls.  Binary32 pools of
+ * struct (WN_EINVAL on a bad size, a flag other than 0/1, high_occupancy with
+ * nontemporal_stores, or wgs_per_cu > 16) and applies to later calls.  Binary32 pools of
  * 1024..8192 values have every choice; other shapes ignore them.  Defaults:
  * the choices measured fastest for binary32 pools on MI355X. */
 wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t);
 wn_status wn_get_tuning(wn_gen *g, wn_tuning *t);
+
+/* Autotune the launch choices for one request shape: run the request once per
+ * candidate (LDS buffering, store kind, register cap, persistent grid size),
+ * timed with HIP events on hip_stream, restoring the generator's state after
+ * each run, and keep the fastest.  The generator's state is unchanged on
+ * return; `out` (same contract as wn_fill) is used as scratch and holds no
+ * defined values afterwards.  *best (nullable) receives the choice, which is
+ * also applied.  Synchronous.  Allocates a temporary copy of the state.
+ * Errors: as wn_fill, plus WN_ENOMEM. */
+wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
+                      void *out, wn_dtype out_dtype, void *hip_stream, wn_tuning *best);
 
 /* Free everything the generator owns.  NULL-safe.  Waits for its work. */
 void wn_destroy(wn_gen *g);

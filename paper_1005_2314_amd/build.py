@@ -12,9 +12,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwn.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("wn_kernels.hip", "wn_bench.hip", "wn_api.cpp")]
-HEADERS = [os.path.join(CSRC, "wn_internal.hpp"), os.path.join(ROOT, "include", "wn.h"),
-           os.path.join(ROOT, "include", "wn_bench.h")]
+SOURCES = [os.path.join(CSRC, f) for f in
+           ("wn_launch_f32.hip", "wn_launch_f64.hip", "wn_bench.hip", "wn_api.cpp")]
+HEADERS = [os.path.join(CSRC, "wn_internal.hpp"), os.path.join(CSRC, "wn_device.hpp"),
+           os.path.join(ROOT, "include", "wn.h"), os.path.join(ROOT, "include", "wn_bench.h")]
+BUILD_DIR = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -26,8 +28,24 @@ FLAGS = [
 ]
 
 
+def _compile(src: str, verbose: bool) -> str:
+    """Compile one source to an object in _build/, keeping the device assembly
+    (*-hip-amdgcn-amd-amdhsa-gfx950.s) beside it for the ISA guard."""
+    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], "-save-temps=obj", "-c", "-x", "hip",
+           src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True, cwd=BUILD_DIR)
+    return obj
+
+
 def build(verbose: bool = False) -> str:
-    cmd = [HIPCC, *FLAGS, "-x", "hip", *SOURCES, "-o", LIB + ".tmp"]
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
+        objs = list(pool.map(lambda src: _compile(src, verbose), SOURCES))
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -35,11 +53,21 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def device_asm_files():
+    """Device assembly kept by the last build, one per HIP source."""
+    out = []
+    for src in SOURCES:
+        if src.endswith(".hip"):
+            stem = os.path.splitext(os.path.basename(src))[0]
+            out.append(os.path.join(BUILD_DIR, f"{stem}-hip-amdgcn-amd-amdhsa-gfx950.s"))
+    return out
+
+
 def is_stale() -> bool:
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(p) > t for p in SOURCES + HEADERS)
+    return any(os.path.getmtime(p) > t for p in SOURCES + HEADERS + [__file__])
 
 
 if __name__ == "__main__":

@@ -2,7 +2,7 @@
 // lists and launches.  Declared in include/wn.h.
 //
 // Nothing here computes normals: every step of generation runs in the kernels
-// of wn_kernels.hip.  The host computes only the per-pool-size chi-square
+// of wn_device.hpp.  The host computes only the per-pool-size chi-square
 // constants (Section 5.5) with plain IEEE arithmetic, once per generator.
 
 #include <hip/hip_runtime.h>
@@ -78,6 +78,23 @@ struct ListSlot {
   bool pending = false;
 };
 
+// Staging buffer, device work list and cached graph of one persistent launch.
+// The graph copies the staging buffer to the device list, resets the item
+// counter and runs the persistent kernel; it is replayed while the launch
+// shape (key) stays the same.
+struct PersistentSlot {
+  wn::WorkItem *host = nullptr;
+  wn::WorkItem *dev = nullptr;
+  uint32_t *counter = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+  hipGraphExec_t exec = nullptr;
+  // key of the cached graph
+  uint32_t k_nitems = 0, k_dtype = 0, k_variant = 0, k_grid = 0, k_max_n = 0;
+  void *k_out = nullptr;
+};
+
 }  // namespace
 
 struct wn_gen {
@@ -100,7 +117,15 @@ struct wn_gen {
   ListSlot slots[4];
   unsigned next_slot = 0;
   std::vector<uint8_t> seen;  // duplicate check scratch
-  uint32_t variant = 1;       // non-semantic kernel variant (wn_tuning); LDS double buffer
+  wn::Chi2Consts cc[wn::kNumSizes];  // per pool size 2^4 .. 2^14
+  // launch choices (wn_tuning); defaults: LDS double buffer, graph replay
+  uint32_t variant = 1;
+  uint32_t wgs_per_cu = 0;
+  bool use_graph = true;
+  // persistent launches: two staging/work-list slots, each with a cached graph
+  PersistentSlot pslots[2];
+  unsigned next_pslot = 0;
+  hipStream_t capture_stream = nullptr;
 };
 
 namespace {
@@ -114,7 +139,7 @@ wn::KernelCommon common(const wn_gen *g, uint32_t n) {
   c.R = g->R;
   c.K = g->K;
   c.chi2 = g->chi2;
-  c.cc = chi2_consts(n);
+  for (int i = 0; i < wn::kNumSizes; ++i) c.cc[i] = g->cc[i];
   return c;
 }
 
@@ -127,6 +152,14 @@ void release(wn_gen *g) {
     if (s.dev) (void)hipFree(s.dev);
     if (s.done) (void)hipEventDestroy(s.done);
   }
+  for (auto &s : g->pslots) {
+    if (s.exec) (void)hipGraphExecDestroy(s.exec);
+    if (s.host) (void)hipHostFree(s.host);
+    if (s.dev) (void)hipFree(s.dev);
+    if (s.counter) (void)hipFree(s.counter);
+    if (s.done) (void)hipEventDestroy(s.done);
+  }
+  if (g->capture_stream) (void)hipStreamDestroy(g->capture_stream);
   for (auto *p : g->d_seed_lists)
     if (p) (void)hipFree(p);
   if (g->d_arena) (void)hipFree(g->d_arena);
@@ -273,6 +306,17 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
       release(g);
       return hip_fail(e, "wn_create: events");
     }
+  for (auto &s : g->pslots)
+    if ((e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipMalloc(&s.counter, sizeof(uint32_t))) != hipSuccess) {
+      release(g);
+      return hip_fail(e, "wn_create: persistent slots");
+    }
+  if ((e = hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking)) != hipSuccess) {
+    release(g);
+    return hip_fail(e, "wn_create: capture stream");
+  }
+  for (int i = 0; i < wn::kNumSizes; ++i) g->cc[i] = chi2_consts(16u << i);
   *out_gen = g;
   return WN_OK;
 }
@@ -298,60 +342,135 @@ wn_status wn_seed(wn_gen *g, uint64_t seed, void *hip_stream) {
   return WN_OK;
 }
 
-wn_status wn_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
-                  void *out, wn_dtype out_dtype, void *hip_stream) {
-  if (!g) return fail(WN_EINVAL, "wn_fill: generator is NULL");
+}  // extern "C"
+
+namespace {
+
+// Validation shared by wn_fill and wn_autotune; sets *total.
+wn_status validate_fill(wn_gen *g, const char *who, uint32_t nreq, const uint32_t *streams,
+                        const uint64_t *counts, void *out, wn_dtype out_dtype, uint64_t *total) {
+  if (!g) return fail(WN_EINVAL, "%s: generator is NULL", who);
   if (nreq > 0 && (!streams || !counts))
-    return fail(WN_EINVAL, "wn_fill: streams/counts are NULL with nreq = %u", nreq);
+    return fail(WN_EINVAL, "%s: streams/counts are NULL with nreq = %u", who, nreq);
   if (out_dtype < WN_F64 || out_dtype > WN_F16)
-    return fail(WN_EINVAL, "wn_fill: unknown output dtype %d", int(out_dtype));
+    return fail(WN_EINVAL, "%s: unknown output dtype %d", who, int(out_dtype));
   if (!g->pool_f64 && out_dtype == WN_F64)
-    return fail(WN_ENOTSUP, "wn_fill: binary64 output needs a binary64 pool");
-  uint64_t total = 0;
+    return fail(WN_ENOTSUP, "%s: binary64 output needs a binary64 pool", who);
+  uint64_t sum = 0;
   bool ok = true;
   uint32_t bad = 0;
-  for (uint32_t j = 0; j < nreq && ok; ++j) {
+  for (uint32_t j = 0; j < nreq; ++j) {
     const uint32_t s = streams[j];
-    if (s >= g->num_streams) {
-      ok = false;
-      bad = j;
-      break;
-    }
-    if (g->seen[s]) {
+    if (s >= g->num_streams || g->seen[s] || counts[j] > (uint64_t(1) << 56)) {
       ok = false;
       bad = j;
       break;
     }
     g->seen[s] = 1;
-    if (counts[j] > (uint64_t(1) << 56) || total + counts[j] < total) {
-      ok = false;
-      bad = j;
-      break;
-    }
-    total += counts[j];
+    sum += counts[j];
   }
   for (uint32_t j = 0; j < nreq; ++j)
     if (streams[j] < g->num_streams) g->seen[streams[j]] = 0;
   if (!ok) {
     if (streams[bad] >= g->num_streams)
-      return fail(WN_EINVAL, "wn_fill: request %u names stream %u of %u", bad, streams[bad],
+      return fail(WN_EINVAL, "%s: request %u names stream %u of %u", who, bad, streams[bad],
                   g->num_streams);
     if (counts[bad] > (uint64_t(1) << 56))
-      return fail(WN_EINVAL, "wn_fill: request %u count too large", bad);
-    return fail(WN_EINVAL, "wn_fill: stream %u listed twice", streams[bad]);
+      return fail(WN_EINVAL, "%s: request %u count too large", who, bad);
+    return fail(WN_EINVAL, "%s: stream %u listed twice", who, streams[bad]);
   }
-  if (total > 0 && !out) return fail(WN_EINVAL, "wn_fill: out is NULL with %llu values requested",
-                                     (unsigned long long)total);
-  if (!g->seeded) return fail(WN_ESTATE, "wn_fill: generator not seeded");
-  if (total == 0) return WN_OK;
+  if (sum > 0 && !out)
+    return fail(WN_EINVAL, "%s: out is NULL with %llu values requested", who,
+                (unsigned long long)sum);
+  if (!g->seeded) return fail(WN_ESTATE, "%s: generator not seeded", who);
+  *total = sum;
+  return WN_OK;
+}
 
-  hipError_t e = hipSetDevice(g->device);
-  if (e != hipSuccess) return hip_fail(e, "wn_fill: hipSetDevice");
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  if ((e = order_after_last(g, st)) != hipSuccess) return hip_fail(e, "wn_fill: ordering");
+hipError_t reserve(wn::WorkItem **host, wn::WorkItem **dev, size_t *cap, size_t need) {
+  if (*cap >= need) return hipSuccess;
+  if (*host) (void)hipHostFree(*host);
+  if (*dev) (void)hipFree(*dev);
+  *host = nullptr;
+  *dev = nullptr;
+  *cap = 0;
+  const size_t c = std::max<size_t>(need, 1024);
+  hipError_t e = hipHostMalloc(reinterpret_cast<void **>(host), c * sizeof(wn::WorkItem),
+                               hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(dev), c * sizeof(wn::WorkItem));
+  if (e == hipSuccess) *cap = c;
+  return e;
+}
 
-  // Affine form (streams s0, s0+1, ... with equal counts, one pool size):
-  // no work list upload.
+// Persistent launch of the items (pool sizes >= 1024) already written, longest
+// first, to slot.host[0 .. nitems): replays the slot's graph when the launch
+// shape is unchanged, captures a new one otherwise (or launches directly when
+// graphs are off).
+hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, uint32_t max_n,
+                             void *out, uint32_t dtype, hipStream_t st) {
+  wn::FillArgs a;
+  a.c = common(g, 0);
+  a.items = slot.dev;
+  a.nitems = nitems;
+  a.affine_s0 = 0;
+  a.count_each = 0;
+  a.out = out;
+  a.variant = g->variant;
+  a.counter = slot.counter;
+  int dev = 0, cus = 256;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const uint32_t grid = g->wgs_per_cu ? uint32_t(cus) * g->wgs_per_cu : 0;
+  const size_t bytes = size_t(nitems) * sizeof(wn::WorkItem);
+  if (!g->use_graph) {
+    if ((e = hipMemcpyAsync(slot.dev, slot.host, bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
+      return e;
+    return wn::launch_fill_persistent(a, g->pool_f64, dtype, max_n, grid, st);
+  }
+  const bool hit = slot.exec && slot.k_nitems == nitems && slot.k_dtype == dtype &&
+                   slot.k_variant == g->variant && slot.k_grid == grid && slot.k_max_n == max_n &&
+                   slot.k_out == out;
+  if (!hit) {
+    if (slot.exec) {
+      (void)hipGraphExecDestroy(slot.exec);
+      slot.exec = nullptr;
+    }
+    hipStream_t cs = g->capture_stream;
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    hipError_t e1 = hipMemcpyAsync(slot.dev, slot.host, bytes, hipMemcpyHostToDevice, cs);
+    if (e1 == hipSuccess) e1 = wn::launch_fill_persistent(a, g->pool_f64, dtype, max_n, grid, cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    if (e1 != hipSuccess || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return e1 != hipSuccess ? e1 : e;
+    }
+    e = hipGraphInstantiate(&slot.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      slot.exec = nullptr;
+      return e;
+    }
+    slot.k_nitems = nitems;
+    slot.k_dtype = dtype;
+    slot.k_variant = g->variant;
+    slot.k_grid = grid;
+    slot.k_max_n = max_n;
+    slot.k_out = out;
+  }
+  return hipGraphLaunch(slot.exec, st);
+}
+
+// Enqueue a validated request.  Three forms:
+//  * affine (streams s0, s0+1, ... with equal counts and one pool size): one
+//    workgroup per stream, no work list;
+//  * otherwise, streams with pools >= 1024 go to one persistent launch over a
+//    work list sorted longest first (estimated pools times pool size);
+//  * streams with smaller pools go to one launch per pool size.
+wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
+                       void *out, wn_dtype out_dtype, hipStream_t st) {
+  hipError_t e;
   bool affine = nreq > 0;
   for (uint32_t j = 1; j < nreq && affine; ++j)
     affine = streams[j] == streams[0] + j && counts[j] == counts[0];
@@ -367,74 +486,132 @@ wn_status wn_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint6
     a.count_each = counts[0];
     a.out = out;
     a.variant = g->variant;
+    a.counter = nullptr;
     if ((e = wn::launch_fill(a, g->pool_f64, uint32_t(out_dtype), st)) != hipSuccess)
       return hip_fail(e, "wn_fill: launch");
-    if ((e = record_last(g, st)) != hipSuccess) return hip_fail(e, "wn_fill: event");
     return WN_OK;
   }
 
-  // General form: a work list per pool size, grouped and ordered by size.
-  ListSlot &slot = g->slots[g->next_slot];
-  g->next_slot = (g->next_slot + 1) % 4;
-  if (slot.pending) {
-    if ((e = hipEventSynchronize(slot.done)) != hipSuccess)
-      return hip_fail(e, "wn_fill: staging wait");
-    slot.pending = false;
-  }
-  if (slot.cap < nreq) {
-    if (slot.host) (void)hipHostFree(slot.host);
-    if (slot.dev) (void)hipFree(slot.dev);
-    slot.host = nullptr;
-    slot.dev = nullptr;
-    slot.cap = 0;
-    const size_t cap = std::max<size_t>(nreq, 1024);
-    if ((e = hipHostMalloc(&slot.host, cap * sizeof(wn::WorkItem), hipHostMallocDefault)) !=
-            hipSuccess ||
-        (e = hipMalloc(&slot.dev, cap * sizeof(wn::WorkItem))) != hipSuccess)
-      return hip_fail(e, "wn_fill: work list allocation");
-    slot.cap = cap;
-  }
   std::vector<uint64_t> off(nreq);
   uint64_t acc = 0;
   for (uint32_t j = 0; j < nreq; ++j) {
     off[j] = acc;
     acc += counts[j];
   }
-  // bucket by pool size, keeping request order inside a bucket
-  std::vector<uint32_t> bucket_start(g->sizes.size() + 1, 0);
-  auto size_index = [&](uint32_t n) {
-    return uint32_t(std::lower_bound(g->sizes.begin(), g->sizes.end(), n) - g->sizes.begin());
-  };
-  for (uint32_t j = 0; j < nreq; ++j) bucket_start[size_index(g->pool_n[streams[j]]) + 1]++;
-  for (size_t b = 0; b < g->sizes.size(); ++b) bucket_start[b + 1] += bucket_start[b];
-  std::vector<uint32_t> fillpos(bucket_start.begin(), bucket_start.end() - 1);
+  uint32_t nbig = 0, nsmall = 0, max_n = 1024;
   for (uint32_t j = 0; j < nreq; ++j) {
-    const uint32_t b = size_index(g->pool_n[streams[j]]);
-    wn::WorkItem &it = slot.host[fillpos[b]++];
-    it.stream = streams[j];
-    it.pad = 0;
-    it.count = counts[j];
-    it.out_off = off[j];
+    if (counts[j] == 0) continue;
+    const uint32_t n = g->pool_n[streams[j]];
+    if (n >= 1024) {
+      ++nbig;
+      max_n = std::max(max_n, n);
+    } else {
+      ++nsmall;
+    }
   }
-  if ((e = hipMemcpyAsync(slot.dev, slot.host, nreq * sizeof(wn::WorkItem),
-                          hipMemcpyHostToDevice, st)) != hipSuccess)
-    return hip_fail(e, "wn_fill: work list upload");
-  for (size_t b = 0; b < g->sizes.size(); ++b) {
-    const uint32_t cnt = bucket_start[b + 1] - bucket_start[b];
-    if (cnt == 0) continue;
-    wn::FillArgs a;
-    a.c = common(g, g->sizes[b]);
-    a.items = slot.dev + bucket_start[b];
-    a.nitems = cnt;
-    a.affine_s0 = 0;
-    a.count_each = 0;
-    a.out = out;
-    a.variant = g->variant;
-    if ((e = wn::launch_fill(a, g->pool_f64, uint32_t(out_dtype), st)) != hipSuccess)
-      return hip_fail(e, "wn_fill: launch");
+
+  if (nbig > 0) {
+    PersistentSlot &slot = g->pslots[g->next_pslot];
+    g->next_pslot = (g->next_pslot + 1) % 2;
+    if (slot.pending) {
+      if ((e = hipEventSynchronize(slot.done)) != hipSuccess)
+        return hip_fail(e, "wn_fill: staging wait");
+      slot.pending = false;
+    }
+    wn::WorkItem *old_dev = slot.dev;
+    if ((e = reserve(&slot.host, &slot.dev, &slot.cap, nbig)) != hipSuccess)
+      return hip_fail(e, "wn_fill: work list allocation");
+    if (slot.dev != old_dev && slot.exec) {  // the cached graph points at the old list
+      (void)hipGraphExecDestroy(slot.exec);
+      slot.exec = nullptr;
+    }
+    std::vector<std::pair<uint64_t, uint32_t>> order;
+    order.reserve(nbig);
+    for (uint32_t j = 0; j < nreq; ++j) {
+      const uint32_t n = g->pool_n[streams[j]];
+      if (counts[j] == 0 || n < 1024) continue;
+      const uint64_t pools = counts[j] / (n - 1) + 1;
+      order.emplace_back(pools * n, j);
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const auto &x, const auto &y) { return x.first > y.first; });
+    for (uint32_t i = 0; i < nbig; ++i) {
+      const uint32_t j = order[i].second;
+      slot.host[i] = wn::WorkItem{streams[j], 0u, counts[j], off[j]};
+    }
+    if ((e = launch_persistent(g, slot, nbig, max_n, out, uint32_t(out_dtype), st)) !=
+        hipSuccess)
+      return hip_fail(e, "wn_fill: persistent launch");
+    if ((e = hipEventRecord(slot.done, st)) != hipSuccess) return hip_fail(e, "wn_fill: event");
+    slot.pending = true;
   }
-  if ((e = hipEventRecord(slot.done, st)) != hipSuccess) return hip_fail(e, "wn_fill: event");
-  slot.pending = true;
+
+  if (nsmall > 0) {
+    ListSlot &slot = g->slots[g->next_slot];
+    g->next_slot = (g->next_slot + 1) % 4;
+    if (slot.pending) {
+      if ((e = hipEventSynchronize(slot.done)) != hipSuccess)
+        return hip_fail(e, "wn_fill: staging wait");
+      slot.pending = false;
+    }
+    if ((e = reserve(&slot.host, &slot.dev, &slot.cap, nsmall)) != hipSuccess)
+      return hip_fail(e, "wn_fill: work list allocation");
+    // bucket by pool size, request order inside a bucket
+    auto size_index = [&](uint32_t n) {
+      return uint32_t(std::lower_bound(g->sizes.begin(), g->sizes.end(), n) - g->sizes.begin());
+    };
+    std::vector<uint32_t> start(g->sizes.size() + 1, 0);
+    for (uint32_t j = 0; j < nreq; ++j) {
+      const uint32_t n = g->pool_n[streams[j]];
+      if (counts[j] > 0 && n < 1024) start[size_index(n) + 1]++;
+    }
+    for (size_t b = 0; b < g->sizes.size(); ++b) start[b + 1] += start[b];
+    std::vector<uint32_t> pos(start.begin(), start.end() - 1);
+    for (uint32_t j = 0; j < nreq; ++j) {
+      const uint32_t n = g->pool_n[streams[j]];
+      if (counts[j] == 0 || n >= 1024) continue;
+      slot.host[pos[size_index(n)]++] = wn::WorkItem{streams[j], 0u, counts[j], off[j]};
+    }
+    if ((e = hipMemcpyAsync(slot.dev, slot.host, nsmall * sizeof(wn::WorkItem),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+      return hip_fail(e, "wn_fill: work list upload");
+    for (size_t b = 0; b < g->sizes.size(); ++b) {
+      const uint32_t cnt = start[b + 1] - start[b];
+      if (cnt == 0) continue;
+      wn::FillArgs a;
+      a.c = common(g, g->sizes[b]);
+      a.items = slot.dev + start[b];
+      a.nitems = cnt;
+      a.affine_s0 = 0;
+      a.count_each = 0;
+      a.out = out;
+      a.variant = g->variant;
+      a.counter = nullptr;
+      if ((e = wn::launch_fill(a, g->pool_f64, uint32_t(out_dtype), st)) != hipSuccess)
+        return hip_fail(e, "wn_fill: launch");
+    }
+    if ((e = hipEventRecord(slot.done, st)) != hipSuccess) return hip_fail(e, "wn_fill: event");
+    slot.pending = true;
+  }
+  return WN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wn_status wn_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
+                  void *out, wn_dtype out_dtype, void *hip_stream) {
+  uint64_t total = 0;
+  wn_status v = validate_fill(g, "wn_fill", nreq, streams, counts, out, out_dtype, &total);
+  if (v != WN_OK) return v;
+  if (total == 0) return WN_OK;
+  hipError_t e = hipSetDevice(g->device);
+  if (e != hipSuccess) return hip_fail(e, "wn_fill: hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if ((e = order_after_last(g, st)) != hipSuccess) return hip_fail(e, "wn_fill: ordering");
+  v = enqueue_fill(g, nreq, streams, counts, out, out_dtype, st);
+  if (v != WN_OK) return v;
   if ((e = record_last(g, st)) != hipSuccess) return hip_fail(e, "wn_fill: event");
   return WN_OK;
 }
@@ -485,10 +662,12 @@ wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t) {
     return fail(WN_EINVAL, "wn_set_tuning: struct_size %u, expected %zu", t->struct_size,
                 sizeof(wn_tuning));
   if (t->lds_double_buffer > 1 || t->nontemporal_stores > 1 || t->high_occupancy > 1 ||
-      (t->high_occupancy && t->nontemporal_stores))
+      t->use_graph > 1 || (t->high_occupancy && t->nontemporal_stores) || t->wgs_per_cu > 16)
     return fail(WN_EINVAL, "wn_set_tuning: flags must be 0 or 1 (high_occupancy without "
-                           "nontemporal_stores)");
+                           "nontemporal_stores), wgs_per_cu <= 16");
   g->variant = t->lds_double_buffer | (t->nontemporal_stores << 1) | (t->high_occupancy << 2);
+  g->wgs_per_cu = t->wgs_per_cu;
+  g->use_graph = t->use_graph != 0;
   return WN_OK;
 }
 
@@ -498,6 +677,120 @@ wn_status wn_get_tuning(wn_gen *g, wn_tuning *t) {
   t->lds_double_buffer = g->variant & 1u;
   t->nontemporal_stores = (g->variant >> 1) & 1u;
   t->high_occupancy = (g->variant >> 2) & 1u;
+  t->wgs_per_cu = g->wgs_per_cu;
+  t->use_graph = g->use_graph ? 1u : 0u;
+  return WN_OK;
+}
+
+wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
+                      void *out, wn_dtype out_dtype, void *hip_stream, wn_tuning *best) {
+  uint64_t total = 0;
+  wn_status v = validate_fill(g, "wn_autotune", nreq, streams, counts, out, out_dtype, &total);
+  if (v != WN_OK) return v;
+  wn_tuning cur;
+  wn_get_tuning(g, &cur);
+  if (total == 0) {
+    if (best) *best = cur;
+    return WN_OK;
+  }
+  hipError_t e = hipSetDevice(g->device);
+  if (e != hipSuccess) return hip_fail(e, "wn_autotune: hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if ((e = order_after_last(g, st)) != hipSuccess) return hip_fail(e, "wn_autotune: ordering");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "wn_autotune: sync");
+
+  // which form will the request take?
+  bool affine = nreq > 0;
+  for (uint32_t j = 1; j < nreq && affine; ++j)
+    affine = streams[j] == streams[0] + j && counts[j] == counts[0] &&
+             g->pool_n[streams[j]] == g->pool_n[streams[0]];
+  std::vector<wn_tuning> cands;
+  auto add = [&](uint32_t db, uint32_t nt, uint32_t oc, uint32_t wpc) {
+    wn_tuning t = cur;
+    t.lds_double_buffer = db;
+    t.nontemporal_stores = nt;
+    t.high_occupancy = oc;
+    t.wgs_per_cu = wpc;
+    cands.push_back(t);
+  };
+  if (affine) {
+    for (uint32_t db = 0; db < 2; ++db)
+      for (uint32_t oc = 0; oc < 2; ++oc) add(db, 0, oc, cur.wgs_per_cu);
+    add(1, 1, 0, cur.wgs_per_cu);
+  } else {
+    for (uint32_t db = 0; db < 2; ++db)
+      for (uint32_t wpc : {0u, 2u, 3u, 4u, 6u, 8u}) add(db, 0, 0, wpc);
+    add(1, 1, 0, 0);
+  }
+
+  // snapshot of the state, restored after every candidate
+  const size_t hdr_bytes = sizeof(wn::StreamHdr) * g->num_streams;
+  unsigned char *save = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  auto cleanup = [&]() {
+    if (save) (void)hipFree(save);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+  };
+  if ((e = hipMalloc(&save, g->arena_bytes + hdr_bytes)) != hipSuccess ||
+      (e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "wn_autotune: scratch");
+  }
+  auto restore = [&]() -> hipError_t {
+    hipError_t r = hipMemcpyAsync(g->d_arena, save, g->arena_bytes, hipMemcpyDeviceToDevice, st);
+    if (r == hipSuccess)
+      r = hipMemcpyAsync(g->d_hdr, save + g->arena_bytes, hdr_bytes, hipMemcpyDeviceToDevice, st);
+    return r;
+  };
+  if ((e = hipMemcpyAsync(save, g->d_arena, g->arena_bytes, hipMemcpyDeviceToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(save + g->arena_bytes, g->d_hdr, hdr_bytes, hipMemcpyDeviceToDevice,
+                          st)) != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "wn_autotune: snapshot");
+  }
+  float best_ms = 1e30f;
+  wn_tuning chosen = cur;
+  for (size_t c = 0; c <= cands.size(); ++c) {
+    // candidate 0 is run once untimed first to warm caches and code objects
+    const wn_tuning &t = cands[c == 0 ? 0 : c - 1];
+    wn_set_tuning(g, &t);
+    float ms = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      if ((e = hipEventRecord(t0, st)) != hipSuccess) break;
+      v = enqueue_fill(g, nreq, streams, counts, out, out_dtype, st);
+      if (v != WN_OK) {
+        wn_set_tuning(g, &cur);
+        (void)restore();
+        (void)hipStreamSynchronize(st);
+        cleanup();
+        return v;
+      }
+      if ((e = hipEventRecord(t1, st)) != hipSuccess || (e = restore()) != hipSuccess ||
+          (e = hipStreamSynchronize(st)) != hipSuccess)
+        break;
+      float m = 0.f;
+      if ((e = hipEventElapsedTime(&m, t0, t1)) != hipSuccess) break;
+      ms = std::min(ms, m);
+    }
+    if (e != hipSuccess) break;
+    if (c > 0 && ms < best_ms) {
+      best_ms = ms;
+      chosen = t;
+    }
+  }
+  if (e != hipSuccess) {
+    wn_set_tuning(g, &cur);
+    (void)restore();
+    (void)hipStreamSynchronize(st);
+    cleanup();
+    return hip_fail(e, "wn_autotune: run");
+  }
+  wn_set_tuning(g, &chosen);
+  cleanup();
+  if ((e = record_last(g, st)) != hipSuccess) return hip_fail(e, "wn_autotune: event");
+  if (best) *best = chosen;
   return WN_OK;
 }
 

@@ -75,7 +75,9 @@ __global__ __launch_bounds__(kBlock) void k_traffic(unsigned char *__restrict__ 
   uint64_t obase = uint64_t(j) * per_stream;
   uint64_t count = per_stream;
   while (count > 0) {
-    const uint32_t take = count < uint64_t(n - 1) ? uint32_t(count) : n - 1;
+    // 32-bit min: no 64-bit compare-and-select of a uniform value
+    const uint32_t big = uint32_t((0ull - (count >> 32)) >> 32);
+    const uint32_t take = min(uint32_t(count) | big, n - 1);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll

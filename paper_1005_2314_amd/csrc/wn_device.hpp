@@ -1,4 +1,6 @@
-// gfx950 kernels of the Wallace maximum-entropy normal generator
+// gfx950 device code of the Wallace maximum-entropy normal generator
+// (included by the per-pool-type launch units wn_launch_f32.hip and
+// wn_launch_f64.hip)
 // (R. P. Brent, "Some Comments on C. S. Wallace's Random Number Generators",
 // Section 5).
 //
@@ -27,12 +29,16 @@
 // rounded IEEE operation in the stated order, matching a scalar CPU
 // evaluation bit for bit.
 
+#pragma once
+
 #include "wn_internal.hpp"
 
+// Internal linkage: each launch unit gets its own copy of these definitions.
 namespace wn {
 namespace {
 
 constexpr uint32_t kBlock = 256;
+constexpr size_t kMaxLds = 160 * 1024;  // LDS per compute unit (gfx950)
 
 // ---- uniform source (Sections 3 and 5.8) -----------------------------------
 // xorshift64 with shifts (13, 7, 17); the result is the new state.
@@ -123,6 +129,40 @@ __device__ __forceinline__ double chi2_sample(const Chi2Consts &c, uint32_t mode
   // (A*(x*x - 1) + b*x) + nu
   const double t1 = __dmul_rn(c.A, __dsub_rn(__dmul_rn(x, x), 1.0));
   return __dadd_rn(__dadd_rn(t1, __dmul_rn(c.b, x)), c.nu);
+}
+
+// ---- cross-lane moves of binary64 values --------------------------------------------
+// DPP (data-parallel primitive) reads of another lane's register, as two 32-bit
+// moves.  Controls: quad_perm [1,0,3,2] (0xB1) and [2,3,0,1] (0x4E) exchange
+// neighbours and pairs inside a group of 4 lanes; row_half_mirror (0x141)
+// reverses each group of 8, row_mirror (0x140) each row of 16, so after the
+// first two steps every lane sees a lane of the other half of its group.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = uint64_t(__double_as_longlong(v));
+  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(u)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(u >> 32)), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const uint64_t u = uint64_t(__double_as_longlong(v));
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u)), lane));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u >> 32)), lane));
+  return __longlong_as_double(int64_t((uint64_t(hi) << 32) | lo));
+}
+
+// Balanced pairwise sum over the 64 lanes of a full wave, lane order: four
+// levels inside rows of 16 lanes (each lane adds the matching lane of the
+// other half of its group; addition commutes, so both halves hold the same
+// bits), then (row0 + row1) + (row2 + row3).  Every lane returns the sum.
+__device__ __forceinline__ double wave_pairwise_sum(double v) {
+  v = __dadd_rn(v, dpp_f64<0xB1>(v));
+  v = __dadd_rn(v, dpp_f64<0x4E>(v));
+  v = __dadd_rn(v, dpp_f64<0x141>(v));
+  v = __dadd_rn(v, dpp_f64<0x140>(v));
+  return __dadd_rn(__dadd_rn(readlane_f64(v, 0), readlane_f64(v, 16)),
+                   __dadd_rn(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
 // ---- output casts (round to nearest even) ---------------------------------------
@@ -284,8 +324,8 @@ struct Engine {
 
   // Sum of squares of the pool held in y: running sum over this thread's
   // elements in increasing index order, then a balanced pairwise tree over
-  // the BD threads (lanes by xor butterflies, then the waves).  Ends with a
-  // barrier; every thread returns the same value.
+  // the BD threads (lanes of a wave, then the waves).  Ends with a barrier;
+  // every thread returns the same value.
   __device__ __forceinline__ double sumsq() {
     double acc = 0.0;
 #pragma unroll
@@ -293,8 +333,11 @@ struct Engine {
 #pragma unroll
       for (int c = 0; c < NQ; ++c) acc = sq_add(acc, y[c][m]);
     const uint32_t B = bd();
-    const uint32_t wl = B < 64 ? B : 64;
-    for (uint32_t w = 1; w < wl; w <<= 1) acc = __dadd_rn(acc, __shfl_xor(acc, int(w)));
+    if (B >= 64) {
+      acc = wave_pairwise_sum(acc);
+    } else {
+      for (uint32_t w = 1; w < B; w <<= 1) acc = __dadd_rn(acc, __shfl_xor(acc, int(w)));
+    }
     if (B > 64 && (tid & 63) == 0) red[tid >> 6] = acc;
     __syncthreads();
     if (B == 128) return __dadd_rn(red[0], red[1]);
@@ -349,6 +392,16 @@ __device__ __forceinline__ Engine<T, NQ, SMALL, DB> make_engine(unsigned char *s
   e.L = n / 4;
   e.tid = threadIdx.x;
   return e;
+}
+
+// min(count, room) for a wave-uniform 64-bit count, in 32-bit arithmetic with
+// no compare.  gfx950 has no scalar 64-bit less-than; written as a compare and
+// select, the compiler has been seen to evaluate the compare into VCC but take
+// the select from a stale SCC (which made the persistent kernel emit whole
+// requests from one pool).
+__device__ __forceinline__ uint32_t take_of(uint64_t count, uint32_t room) {
+  const uint32_t big = uint32_t((0ull - (count >> 32)) >> 32);  // all ones if count >= 2^32
+  return min(uint32_t(count) | big, room);
 }
 
 __device__ __forceinline__ void flag_fault(uint32_t *err, double Q) {
@@ -412,34 +465,22 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
 }
 
 // ---- generation ---------------------------------------------------------------------
-// Work item: continue stream s for `count` values written from out[obase].
+// Work item: continue stream s (pool size n, NQ = n/1024 quadruples per
+// thread, or the SMALL layout) for `count` values written from out[obase].
 // Pool production (Section 5.5): optional renormalisation every K pools with
 // the previous sum of squares, R passes, binary64 sum of squares Q, a
 // chi-square sample S from the previous pool's withheld scaled value,
 // f = sqrt(S / Q); the n-1 first positions are emitted as T(P[i] * T(f)) and
 // the withheld value f * P[n-1] feeds the next sample.  The stored pool is
-// never scaled.
-template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE>
-__global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t j = blockIdx.x;
-  uint32_t s;
-  uint64_t count, obase;
-  if (a.items) {
-    const WorkItem it = a.items[j];
-    s = it.stream;
-    count = it.count;
-    obase = it.out_off;
-  } else {
-    s = a.affine_s0 + j;
-    count = a.count_each;
-    obase = uint64_t(j) * a.count_each;
-  }
-  if (count == 0) return;
-
-  const uint32_t n = a.c.n;
-  auto e = make_engine<T, NQ, SMALL, DB>(smem, n);
+// never scaled.  Starts and ends without a barrier of its own: the caller
+// separates two items on one workgroup by a barrier.
+template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT>
+__device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem, uint32_t s,
+                                          uint64_t count, uint64_t obase) {
   StreamHdr *h = a.c.hdr + s;
+  const uint32_t n = h->n;
+  auto e = make_engine<T, NQ, SMALL, DB>(smem, n);
+  const Chi2Consts &cc = a.c.cc[__builtin_ctz(n) - 4];
   uint64_t xs = h->xs;
   uint64_t k = h->k;
   double f = h->f;
@@ -453,7 +494,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
   __syncthreads();
 
   if (cursor < n - 1) {
-    const uint32_t take = count < uint64_t(n - 1 - cursor) ? uint32_t(count) : n - 1 - cursor;
+    const uint32_t take = take_of(count, n - 1 - cursor);
     e.template emit<NT>(out, obase, cursor, cursor + take, T(f));
     obase += take;
     count -= take;
@@ -473,13 +514,13 @@ __global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
     const double Q = e.sumsq();
     const double last = double(e.cur[n - 1]);
     double fk = 1.0;
-    if (a.c.chi2 != kChi2Off) fk = __dsqrt_rn(__ddiv_rn(chi2_sample(a.c.cc, a.c.chi2, xnext), Q));
+    if (a.c.chi2 != kChi2Off) fk = __dsqrt_rn(__ddiv_rn(chi2_sample(cc, a.c.chi2, xnext), Q));
     if (e.tid == 0) flag_fault(a.c.err, Q);
     f = fk;
     xnext = __dmul_rn(fk, last);
     qlast = Q;
     k += 1;
-    const uint32_t take = count < uint64_t(n - 1) ? uint32_t(count) : n - 1;
+    const uint32_t take = take_of(count, n - 1);
     e.template emit<NT>(out, obase, 0, take, T(f));
     obase += take;
     count -= take;
@@ -497,106 +538,64 @@ __global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
   }
 }
 
-// ---- dispatch ------------------------------------------------------------------------
-size_t lds_bytes(uint32_t n, bool pool_f64, bool db) {
-  return size_t(n) * (pool_f64 ? 8 : 4) * (db ? 2 : 1) + 4 * sizeof(double);
+// One workgroup per work item (all items of the launch share one pool size).
+template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE>
+__global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t j = blockIdx.x;
+  uint32_t s;
+  uint64_t count, obase;
+  if (a.items) {
+    const WorkItem it = a.items[j];
+    s = it.stream;
+    count = it.count;
+    obase = it.out_off;
+  } else {
+    s = a.affine_s0 + j;
+    count = a.count_each;
+    obase = uint64_t(j) * a.count_each;
+  }
+  if (count == 0) return;
+  fill_item<T, O, NQ, SMALL, DB, NT>(a, smem, s, count, obase);
 }
 
-template <typename Kern>
-hipError_t prepare(Kern kern, size_t lds) {
-  if (lds > 65536)
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-  return hipSuccess;
-}
-
-template <typename T, int NQ, bool SMALL>
-hipError_t seed_t(const SeedArgs &a, hipStream_t st) {
-  const size_t lds = lds_bytes(a.c.n, sizeof(T) == 8, false);
-  auto kern = k_seed<T, NQ, SMALL>;
-  hipError_t e = prepare(kern, lds);
-  if (e != hipSuccess) return e;
-  const uint32_t block = SMALL ? a.c.n / 4 : kBlock;
-  hipLaunchKernelGGL(kern, dim3(a.nstreams), dim3(block), lds, st, a);
-  return hipGetLastError();
-}
-
-template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE = 1>
-hipError_t fill_t(const FillArgs &a, hipStream_t st) {
-  const size_t lds = lds_bytes(a.c.n, sizeof(T) == 8, DB);
-  auto kern = k_fill<T, O, NQ, SMALL, DB, NT, WPE>;
-  hipError_t e = prepare(kern, lds);
-  if (e != hipSuccess) return e;
-  const uint32_t block = SMALL ? a.c.n / 4 : kBlock;
-  hipLaunchKernelGGL(kern, dim3(a.nitems), dim3(block), lds, st, a);
-  return hipGetLastError();
-}
-
-// Non-semantic variants (identical results): bit 0 double-buffered LDS,
-// bit 1 nontemporal output stores, bit 2 at most 64 VGPRs (8 waves per SIMD).  Binary32 pools of 1024..8192 values have
-// all four; every other shape runs variant 0.
-template <typename T, typename O, int NQ>
-hipError_t fill_v(const FillArgs &a, hipStream_t st) {
-  if constexpr (sizeof(T) == 4 && NQ <= 8) {
-    switch (a.variant & 7u) {
-      case 1: return fill_t<T, O, NQ, false, true, false>(a, st);
-      case 2: return fill_t<T, O, NQ, false, false, true>(a, st);
-      case 3: return fill_t<T, O, NQ, false, true, true>(a, st);
-      case 4: return fill_t<T, O, NQ, false, false, false, 8>(a, st);
-      case 5: return fill_t<T, O, NQ, false, true, false, 8>(a, st);
-      default: break;
+// Persistent form: a fixed grid of workgroups pops work items (pool sizes
+// 1024 .. 1024*MAXNQ, mixed) from a device counter in the order of the list
+// (the host sorts it longest first).  Every workgroup leaves the loop once the
+// counter passes the end of the list.
+template <typename T, typename O, int MAXNQ, bool DB, bool NT>
+__global__ __launch_bounds__(kBlock) void k_fill_persistent(FillArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t next_item;
+  for (;;) {
+    __syncthreads();  // the previous item's last LDS reads are done
+    if (threadIdx.x == 0) next_item = atomicAdd(a.counter, 1u);
+    __syncthreads();
+    const uint32_t j = next_item;
+    if (j >= a.nitems) break;
+    const WorkItem it = a.items[j];
+    if (it.count == 0) continue;
+    switch (a.c.hdr[it.stream].n) {
+      case 1024: fill_item<T, O, 1, false, DB, NT>(a, smem, it.stream, it.count, it.out_off); break;
+      case 2048:
+        if constexpr (MAXNQ >= 2) fill_item<T, O, 2, false, DB, NT>(a, smem, it.stream, it.count, it.out_off);
+        break;
+      case 4096:
+        if constexpr (MAXNQ >= 4) fill_item<T, O, 4, false, DB, NT>(a, smem, it.stream, it.count, it.out_off);
+        break;
+      case 8192:
+        if constexpr (MAXNQ >= 8) fill_item<T, O, 8, false, DB, NT>(a, smem, it.stream, it.count, it.out_off);
+        break;
+      default:
+        if constexpr (MAXNQ >= 16) fill_item<T, O, 16, false, DB, NT>(a, smem, it.stream, it.count, it.out_off);
+        break;
     }
   }
-  return fill_t<T, O, NQ, false, false, false>(a, st);
 }
 
-template <typename T>
-hipError_t seed_n(const SeedArgs &a, hipStream_t st) {
-  switch (a.c.n) {
-    case 1024: return seed_t<T, 1, false>(a, st);
-    case 2048: return seed_t<T, 2, false>(a, st);
-    case 4096: return seed_t<T, 4, false>(a, st);
-    case 8192: return seed_t<T, 8, false>(a, st);
-    case 16384: return seed_t<T, 16, false>(a, st);
-    default: return seed_t<T, 1, true>(a, st);
-  }
-}
-
-template <typename T, typename O>
-hipError_t fill_n(const FillArgs &a, hipStream_t st) {
-  switch (a.c.n) {
-    case 1024: return fill_v<T, O, 1>(a, st);
-    case 2048: return fill_v<T, O, 2>(a, st);
-    case 4096: return fill_v<T, O, 4>(a, st);
-    case 8192: return fill_v<T, O, 8>(a, st);
-    case 16384: return fill_v<T, O, 16>(a, st);
-    default: return fill_t<T, O, 1, true, false, false>(a, st);
-  }
+__global__ void k_reset_counter(uint32_t *ctr) {
+  if (threadIdx.x == 0) *ctr = 0u;
 }
 
 }  // namespace
-
-hipError_t launch_seed(const SeedArgs &a, bool pool_f64, hipStream_t s) {
-  if (a.nstreams == 0) return hipSuccess;
-  return pool_f64 ? seed_n<double>(a, s) : seed_n<float>(a, s);
-}
-
-hipError_t launch_fill(const FillArgs &a, bool pool_f64, uint32_t out_dtype, hipStream_t s) {
-  if (a.nitems == 0) return hipSuccess;
-  if (pool_f64) {
-    switch (out_dtype) {
-      case kOutF64: return fill_n<double, double>(a, s);
-      case kOutF32: return fill_n<double, float>(a, s);
-      case kOutBF16: return fill_n<double, Bf16>(a, s);
-      default: return fill_n<double, Half>(a, s);
-    }
-  }
-  switch (out_dtype) {
-    case kOutF32: return fill_n<float, float>(a, s);
-    case kOutBF16: return fill_n<float, Bf16>(a, s);
-    case kOutF16: return fill_n<float, Half>(a, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
 }  // namespace wn

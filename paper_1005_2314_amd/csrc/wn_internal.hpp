@@ -1,5 +1,5 @@
 // Internal interface between the C ABI (wn_api.cpp) and the gfx950 kernels
-// (wn_kernels.hip).  Not installed; plain structs only.
+// (wn_device.hpp, wn_launch_*.hip).  Not installed; plain structs only.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,15 +38,17 @@ struct WorkItem {
 enum : uint32_t { kChi2Cubic = 0, kChi2Off = 1, kChi2Fisher = 2, kChi2WH = 3 };
 enum : uint32_t { kOutF64 = 0, kOutF32 = 1, kOutBF16 = 2, kOutF16 = 3 };
 
+constexpr int kNumSizes = 11;  // pool sizes 2^4 .. 2^14
+
 struct KernelCommon {
   StreamHdr *hdr;
   unsigned char *arena;
   uint32_t *err;  // device fault word (bit 0: non-finite or zero sum of squares)
-  uint32_t n;     // pool size of every item of this launch
+  uint32_t n;     // pool size of every item of a one-size launch (0 for mixed sizes)
   uint32_t R;     // passes per emitted pool
   uint32_t K;     // renormalisation period (0 = never)
   uint32_t chi2;  // chi-square mode
-  Chi2Consts cc;
+  Chi2Consts cc[kNumSizes];  // per pool size, index log2(n) - 4
 };
 
 struct SeedArgs {
@@ -65,10 +67,34 @@ struct FillArgs {
   uint64_t count_each;
   void *out;
   uint32_t variant;       // non-semantic kernel variant (bit 0: LDS double buffer, bit 1: NT stores)
+  uint32_t *counter;      // persistent form: next work item (reset by the launch)
 };
 
-// Launchers (wn_kernels.hip).  Return hipSuccess or the launch error.
-hipError_t launch_seed(const SeedArgs &a, bool pool_f64, hipStream_t s);
-hipError_t launch_fill(const FillArgs &a, bool pool_f64, uint32_t out_dtype, hipStream_t s);
+// Launchers, one translation unit per pool type (wn_launch_f32.hip,
+// wn_launch_f64.hip).  Return hipSuccess or the launch error.
+hipError_t f32_seed(const SeedArgs &a, hipStream_t s);
+hipError_t f64_seed(const SeedArgs &a, hipStream_t s);
+hipError_t f32_fill(const FillArgs &a, uint32_t out_dtype, hipStream_t s);
+hipError_t f64_fill(const FillArgs &a, uint32_t out_dtype, hipStream_t s);
+// Persistent launch over items of pool sizes 1024..max_n (mixed), `grid`
+// workgroups (0 = as many as can be resident); resets a.counter first (a
+// kernel, not a memset, so that the two launches can be captured in a graph).
+hipError_t f32_fill_persistent(const FillArgs &a, uint32_t out_dtype, uint32_t max_n,
+                               uint32_t grid, hipStream_t s);
+hipError_t f64_fill_persistent(const FillArgs &a, uint32_t out_dtype, uint32_t max_n,
+                               uint32_t grid, hipStream_t s);
+
+inline hipError_t launch_seed(const SeedArgs &a, bool pool_f64, hipStream_t s) {
+  return pool_f64 ? f64_seed(a, s) : f32_seed(a, s);
+}
+inline hipError_t launch_fill(const FillArgs &a, bool pool_f64, uint32_t out_dtype,
+                              hipStream_t s) {
+  return pool_f64 ? f64_fill(a, out_dtype, s) : f32_fill(a, out_dtype, s);
+}
+inline hipError_t launch_fill_persistent(const FillArgs &a, bool pool_f64, uint32_t out_dtype,
+                                         uint32_t max_n, uint32_t grid, hipStream_t s) {
+  return pool_f64 ? f64_fill_persistent(a, out_dtype, max_n, grid, s)
+                  : f32_fill_persistent(a, out_dtype, max_n, grid, s);
+}
 
 }  // namespace wn

@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "WN_OK", 1: "WN_EINVAL", 2: "WN_ENOMEM", 3: "WN_EDEVICE", 4: 
 
 # every symbol include/wn.h and include/wn_bench.h declare
 EXPORTED = ("wn_create", "wn_seed", "wn_fill", "wn_sync", "wn_get_stream", "wn_destroy",
-            "wn_last_error", "wn_version", "wn_set_tuning", "wn_get_tuning", "wn_bench_store", "wn_bench_traffic",
+            "wn_last_error", "wn_version", "wn_set_tuning", "wn_get_tuning", "wn_autotune", "wn_bench_store", "wn_bench_traffic",
             "wn_bench_box_muller")
 
 
@@ -39,7 +39,8 @@ class wn_stream_info(C.Structure):
 
 class wn_tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("lds_double_buffer", C.c_uint32),
-                ("nontemporal_stores", C.c_uint32), ("high_occupancy", C.c_uint32)]
+                ("nontemporal_stores", C.c_uint32), ("high_occupancy", C.c_uint32),
+                ("wgs_per_cu", C.c_uint32), ("use_graph", C.c_uint32)]
 
 
 class WnError(RuntimeError):
@@ -80,6 +81,9 @@ def load():
         L.wn_set_tuning.restype = C.c_int
         L.wn_get_tuning.argtypes = [vp, C.POINTER(wn_tuning)]
         L.wn_get_tuning.restype = C.c_int
+        L.wn_autotune.argtypes = [vp, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
+                                  vp, C.c_int, vp, C.POINTER(wn_tuning)]
+        L.wn_autotune.restype = C.c_int
         L.wn_bench_store.argtypes = [vp, C.c_uint64, C.c_uint32, vp]
         L.wn_bench_store.restype = C.c_int
         L.wn_bench_traffic.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.c_uint64, vp]
@@ -231,8 +235,13 @@ class Generator:
     def sync(self):
         wn_sync(self._h)
 
-    def set_tuning(self, lds_double_buffer=None, nontemporal_stores=None, high_occupancy=None):
+    def set_tuning(self, lds_double_buffer=None, nontemporal_stores=None, high_occupancy=None,
+                   wgs_per_cu=None, use_graph=None):
         t = self.tuning()
+        if wgs_per_cu is not None:
+            t.wgs_per_cu = int(wgs_per_cu)
+        if use_graph is not None:
+            t.use_graph = int(use_graph)
         if lds_double_buffer is not None:
             t.lds_double_buffer = int(lds_double_buffer)
         if nontemporal_stores is not None:
@@ -244,6 +253,21 @@ class Generator:
     def tuning(self):
         t = wn_tuning()
         check(load().wn_get_tuning(self._h, C.byref(t)))
+        return t
+
+    def autotune(self, out, streams, counts, stream=None):
+        """Pick the fastest launch choices for this request shape (state unchanged)."""
+        import torch
+        dt = {torch.float64: WN_F64, torch.float32: WN_F32, torch.bfloat16: WN_BF16,
+              torch.float16: WN_F16}[out.dtype]
+        streams = np.ascontiguousarray(streams, np.uint32)
+        counts = np.ascontiguousarray(counts, np.uint64)
+        t = wn_tuning()
+        check(load().wn_autotune(self._h, streams.size,
+                                 streams.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                 counts.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                 C.c_void_p(out.data_ptr()), dt, self._stream_handle(stream),
+                                 C.byref(t)))
         return t
 
     def stream_state(self, s: int):

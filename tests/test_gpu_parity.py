@@ -186,3 +186,81 @@ def test_tuning_rejects_bad_values():
     with pytest.raises(W.WnError) as ei:
         W.check(W.load().wn_set_tuning(g._h, W.C.byref(t)))
     assert ei.value.status == W.WN_EINVAL
+
+
+def _request(rng, ns, max_count):
+    order = rng.permutation(ns).astype(np.uint32)
+    counts = rng.integers(0, max_count, size=ns).astype(np.uint64)
+    return order, counts
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+@pytest.mark.parametrize("wgs", [0, 1, 3])
+def test_persistent_launch_shapes_bit_exact(use_graph, wgs):
+    sizes = np.array([1024, 2048, 4096] * 7, np.uint32)
+    p = Pair(len(sizes), pool_n=sizes, R=2, seed=13)
+    p.gpu.set_tuning(use_graph=use_graph, wgs_per_cu=wgs)
+    rng = np.random.default_rng(wgs)
+    order, counts = _request(rng, len(sizes), 20000)
+    for call in range(3):  # the same shape again: the cached graph is replayed
+        g, o = p.fill(order, counts)
+        assert_bits_equal(g, o, f"call {call}")
+        import torch
+        torch.zeros(1 << 20, device="cuda").add_(1.0)  # eager work between replays
+    order2, counts2 = _request(rng, len(sizes), 5000)  # a new shape: a new graph
+    g, o = p.fill(order2, counts2)
+    assert_bits_equal(g, o, "new shape")
+
+
+def test_persistent_with_small_pools_mixed_in():
+    sizes = np.array([64, 1024, 256, 4096, 16, 2048, 16384, 512], np.uint32)
+    p = Pair(len(sizes), pool_n=sizes, R=2, seed=2)
+    rng = np.random.default_rng(5)
+    for _ in range(2):
+        order, counts = _request(rng, len(sizes), 40000)
+        g, o = p.fill(order, counts, W.WN_BF16)
+        assert_bits_equal(g, o, "mixed with small pools")
+
+
+def test_autotune_keeps_state_and_results():
+    import torch
+    sizes = np.array([1024, 2048, 4096] * 10, np.uint32)
+    p = Pair(len(sizes), pool_n=sizes, R=2, seed=17)
+    order, counts = _request(np.random.default_rng(8), len(sizes), 30000)
+    g, o = p.fill(order, counts)
+    assert_bits_equal(g, o, "before tuning")
+    scratch = torch.empty(int(counts.sum()), dtype=torch.float32, device="cuda")
+    t = p.gpu.autotune(scratch, order, counts)
+    assert t.wgs_per_cu <= 16 and t.lds_double_buffer in (0, 1)
+    now = p.gpu.tuning()
+    assert (now.lds_double_buffer, now.wgs_per_cu) == (t.lds_double_buffer, t.wgs_per_cu)
+    g, o = p.fill(order, counts)
+    assert_bits_equal(g, o, "after tuning")
+    # uniform requests take the one-workgroup-per-stream form
+    g2, o2 = p.fill(np.arange(len(sizes)), [0] * len(sizes))
+    assert g2.size == 0
+
+
+def test_uneven_batch_full_size_sampled():
+    """10000 streams, counts log-uniform in [2^10, 2^22), pools of 1024/2048/4096:
+    one persistent launch; the longest and a spread of other streams are checked."""
+    import torch
+    from gpu_util import to_numpy_bits
+    from paper_1005_2314_amd import inputs
+    w = inputs.uneven()
+    p = Pair(w["num_streams"], pool_n=w["pool_n"], R=w["R"], seed=w["seed"])
+    counts = w["counts"]
+    y = p.gpu.fill(w["streams"], counts, W.WN_F32)
+    torch.cuda.synchronize()
+    p.gpu.sync()
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    longest = np.argsort(counts)[-3:]
+    sample = np.unique(np.concatenate([longest, inputs.sample_streams(w["num_streams"], 6)]))
+    from oracle import oracle as O
+    o = p.orc.fill(sample, counts[sample], O.F32)
+    at = 0
+    for s in sample:
+        c = int(counts[s])
+        g = to_numpy_bits(y[offs[s]: offs[s] + c])
+        assert_bits_equal(g, bits(o[at: at + c]), f"stream {s} ({c} values)")
+        at += c

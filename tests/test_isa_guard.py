@@ -1,0 +1,22 @@
+"""The device code must not contain selects that can read a stale SCC (see
+paper_1005_2314_amd/isa_check.py); the check cross-compiles on the CPU."""
+from paper_1005_2314_amd import isa_check
+
+
+def test_checker_flags_the_known_bad_sequence():
+    bad = """_Zbad:
+	s_or_b64 exec, exec, s[0:1]
+	v_cmp_lt_u64_e32 vcc, s[52:53], v[26:27]
+	s_cselect_b32 s6, s52, 0x3ff
+"""
+    good = """_Zgood:
+	v_cmp_lt_u64_e32 vcc, s[16:17], v[0:1]
+	s_and_b64 s[0:1], vcc, exec
+	s_cselect_b32 s24, s16, s38
+"""
+    assert isa_check.stale_scc_selects(bad) == [("_Zbad", 4)]
+    assert isa_check.stale_scc_selects(good) == []
+
+
+def test_library_device_code_has_no_stale_scc_select():
+    assert isa_check.check_library_sources() == []
