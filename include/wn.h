@@ -113,6 +113,34 @@ wn_status wn_seed(wn_gen *g, uint64_t seed, void *hip_stream);
 wn_status wn_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
                   void *out, wn_dtype out_dtype, void *hip_stream);
 
+/* Statistics of the values one wn_fill_stats call emits (device memory,
+ * written by the call).  Sums are binary64 in a fixed order that depends only
+ * on the request (not on scheduling), so repeated runs give identical bits.
+ * y is each value as stored in the output type.  For every pool k produced,
+ * D_k = f_k^2 (Q_k - P_k[n-1]^2) - (n - 1) is the sum of squares of its n-1
+ * emitted values (Section 5.5) minus its expected value; successive pools of a
+ * stream (also across calls) form the lag pairs used to detect pool-to-pool
+ * correlation (Sections 5.6, 5.7).  Centring keeps the lag-1 correlation
+ * (t_lag/t_pairs - (t_sum/pools)^2) / variance well conditioned. */
+typedef struct {
+  uint64_t count;        /* values emitted */
+  double moment[4];      /* sum of y, y^2, y^3, y^4 */
+  uint64_t below, above; /* values with y < -8, y >= 8 */
+  uint64_t pools;        /* pools produced */
+  double t_sum, t_sumsq; /* sum of D_k and of D_k^2 over the pools produced */
+  uint64_t t_pairs;      /* pools produced that have a predecessor in their stream */
+  double t_lag;          /* sum of D_k * D_{k-1} over those pools */
+  uint64_t hist[4096];   /* count of values with floor(256 y) + 2048 = bin, y in [-8, 8) */
+} wn_stats;
+
+/* wn_fill plus fused statistics of the emitted values into `stats`
+ * (caller-owned device memory, 8-byte aligned, sizeof(wn_stats); overwritten).
+ * Same semantics and outputs as wn_fill; every count must be below 2^32.
+ * Errors: as wn_fill; WN_EINVAL also for a NULL or misaligned stats pointer or
+ * a count of 2^32 or more. */
+wn_status wn_fill_stats(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
+                        void *out, wn_dtype out_dtype, wn_stats *stats, void *hip_stream);
+
 /* Wait for the generator's outstanding work and report a fault a kernel
  * flagged since the last check (a non-finite or zero sum of squares):
  * WN_EDEVICE with a message, else WN_OK. */

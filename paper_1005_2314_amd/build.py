@@ -13,7 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwn.so")
 SOURCES = [os.path.join(CSRC, f) for f in
-           ("wn_launch_f32.hip", "wn_launch_f64.hip", "wn_bench.hip", "wn_api.cpp")]
+           ("wn_launch_f32.hip", "wn_launch_f64.hip", "wn_stats.hip", "wn_bench.hip",
+            "wn_api.cpp")]
 HEADERS = [os.path.join(CSRC, "wn_internal.hpp"), os.path.join(CSRC, "wn_device.hpp"),
            os.path.join(ROOT, "include", "wn.h"), os.path.join(ROOT, "include", "wn_bench.h")]
 BUILD_DIR = os.path.join(ROOT, "_build")

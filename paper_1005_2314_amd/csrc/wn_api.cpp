@@ -126,6 +126,8 @@ struct wn_gen {
   PersistentSlot pslots[2];
   unsigned next_pslot = 0;
   hipStream_t capture_stream = nullptr;
+  wn::StatsPartial *d_partials = nullptr;  // fused statistics, one per request
+  size_t partials_cap = 0;
 };
 
 namespace {
@@ -160,6 +162,7 @@ void release(wn_gen *g) {
     if (s.done) (void)hipEventDestroy(s.done);
   }
   if (g->capture_stream) (void)hipStreamDestroy(g->capture_stream);
+  if (g->d_partials) (void)hipFree(g->d_partials);
   for (auto *p : g->d_seed_lists)
     if (p) (void)hipFree(p);
   if (g->d_arena) (void)hipFree(g->d_arena);
@@ -407,7 +410,7 @@ hipError_t reserve(wn::WorkItem **host, wn::WorkItem **dev, size_t *cap, size_t 
 // shape is unchanged, captures a new one otherwise (or launches directly when
 // graphs are off).
 hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, uint32_t max_n,
-                             void *out, uint32_t dtype, hipStream_t st) {
+                             void *out, uint32_t dtype, wn::StatsOut *stats, hipStream_t st) {
   wn::FillArgs a;
   a.c = common(g, 0);
   a.items = slot.dev;
@@ -417,13 +420,15 @@ hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, u
   a.out = out;
   a.variant = g->variant;
   a.counter = slot.counter;
+  a.partials = stats ? g->d_partials : nullptr;
+  a.stats = stats;
   int dev = 0, cus = 256;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   const uint32_t grid = g->wgs_per_cu ? uint32_t(cus) * g->wgs_per_cu : 0;
   const size_t bytes = size_t(nitems) * sizeof(wn::WorkItem);
-  if (!g->use_graph) {
+  if (!g->use_graph || stats) {
     if ((e = hipMemcpyAsync(slot.dev, slot.host, bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
       return e;
     return wn::launch_fill_persistent(a, g->pool_f64, dtype, max_n, grid, st);
@@ -469,8 +474,10 @@ hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, u
 //    work list sorted longest first (estimated pools times pool size);
 //  * streams with smaller pools go to one launch per pool size.
 wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
-                       void *out, wn_dtype out_dtype, hipStream_t st) {
+                       void *out, wn_dtype out_dtype, hipStream_t st,
+                       wn::StatsOut *stats = nullptr) {
   hipError_t e;
+  wn::StatsPartial *partials = stats ? g->d_partials : nullptr;
   bool affine = nreq > 0;
   for (uint32_t j = 1; j < nreq && affine; ++j)
     affine = streams[j] == streams[0] + j && counts[j] == counts[0];
@@ -487,6 +494,8 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
     a.out = out;
     a.variant = g->variant;
     a.counter = nullptr;
+    a.partials = partials;
+    a.stats = stats;
     if ((e = wn::launch_fill(a, g->pool_f64, uint32_t(out_dtype), st)) != hipSuccess)
       return hip_fail(e, "wn_fill: launch");
     return WN_OK;
@@ -537,9 +546,9 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
                      [](const auto &x, const auto &y) { return x.first > y.first; });
     for (uint32_t i = 0; i < nbig; ++i) {
       const uint32_t j = order[i].second;
-      slot.host[i] = wn::WorkItem{streams[j], 0u, counts[j], off[j]};
+      slot.host[i] = wn::WorkItem{streams[j], j, counts[j], off[j]};
     }
-    if ((e = launch_persistent(g, slot, nbig, max_n, out, uint32_t(out_dtype), st)) !=
+    if ((e = launch_persistent(g, slot, nbig, max_n, out, uint32_t(out_dtype), stats, st)) !=
         hipSuccess)
       return hip_fail(e, "wn_fill: persistent launch");
     if ((e = hipEventRecord(slot.done, st)) != hipSuccess) return hip_fail(e, "wn_fill: event");
@@ -570,7 +579,7 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
     for (uint32_t j = 0; j < nreq; ++j) {
       const uint32_t n = g->pool_n[streams[j]];
       if (counts[j] == 0 || n >= 1024) continue;
-      slot.host[pos[size_index(n)]++] = wn::WorkItem{streams[j], 0u, counts[j], off[j]};
+      slot.host[pos[size_index(n)]++] = wn::WorkItem{streams[j], j, counts[j], off[j]};
     }
     if ((e = hipMemcpyAsync(slot.dev, slot.host, nsmall * sizeof(wn::WorkItem),
                             hipMemcpyHostToDevice, st)) != hipSuccess)
@@ -587,6 +596,8 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
       a.out = out;
       a.variant = g->variant;
       a.counter = nullptr;
+      a.partials = partials;
+      a.stats = stats;
       if ((e = wn::launch_fill(a, g->pool_f64, uint32_t(out_dtype), st)) != hipSuccess)
         return hip_fail(e, "wn_fill: launch");
     }
@@ -613,6 +624,50 @@ wn_status wn_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint6
   v = enqueue_fill(g, nreq, streams, counts, out, out_dtype, st);
   if (v != WN_OK) return v;
   if ((e = record_last(g, st)) != hipSuccess) return hip_fail(e, "wn_fill: event");
+  return WN_OK;
+}
+
+wn_status wn_fill_stats(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
+                        void *out, wn_dtype out_dtype, wn_stats *stats, void *hip_stream) {
+  static_assert(sizeof(wn_stats) == sizeof(wn::StatsOut), "wn_stats layout");
+  uint64_t total = 0;
+  wn_status v = validate_fill(g, "wn_fill_stats", nreq, streams, counts, out, out_dtype, &total);
+  if (v != WN_OK) return v;
+  if (!stats || reinterpret_cast<uintptr_t>(stats) % 8 != 0)
+    return fail(WN_EINVAL, "wn_fill_stats: stats is NULL or not 8-byte aligned");
+  for (uint32_t j = 0; j < nreq; ++j)
+    if (counts[j] >= (uint64_t(1) << 32))
+      return fail(WN_EINVAL, "wn_fill_stats: request %u counts 2^32 values or more", j);
+  hipError_t e = hipSetDevice(g->device);
+  if (e != hipSuccess) return hip_fail(e, "wn_fill_stats: hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if ((e = order_after_last(g, st)) != hipSuccess) return hip_fail(e, "wn_fill_stats: ordering");
+  const size_t need = std::max<size_t>(nreq, 1);
+  if (g->partials_cap < need) {
+    // the previous buffer may still be read by queued work: wait before freeing
+    if (g->d_partials) {
+      if (g->has_last && (e = hipEventSynchronize(g->last)) != hipSuccess)
+        return hip_fail(e, "wn_fill_stats: wait");
+      (void)hipFree(g->d_partials);
+      g->d_partials = nullptr;
+      g->partials_cap = 0;
+    }
+    if ((e = hipMalloc(&g->d_partials, need * sizeof(wn::StatsPartial))) != hipSuccess)
+      return hip_fail(e, "wn_fill_stats: partials");
+    g->partials_cap = need;
+  }
+  auto *so = reinterpret_cast<wn::StatsOut *>(stats);
+  if ((e = wn::stats_zero(so, st)) != hipSuccess ||
+      (e = wn::zero_words(g->d_partials, uint32_t(need * sizeof(wn::StatsPartial) / 8), st)) !=
+          hipSuccess)
+    return hip_fail(e, "wn_fill_stats: zero");
+  if (total > 0) {
+    v = enqueue_fill(g, nreq, streams, counts, out, out_dtype, st, so);
+    if (v != WN_OK) return v;
+  }
+  if ((e = wn::stats_reduce(g->d_partials, nreq, so, st)) != hipSuccess)
+    return hip_fail(e, "wn_fill_stats: reduce");
+  if ((e = record_last(g, st)) != hipSuccess) return hip_fail(e, "wn_fill_stats: event");
   return WN_OK;
 }
 

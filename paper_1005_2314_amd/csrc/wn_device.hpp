@@ -211,6 +211,41 @@ struct Cast<Half> {
   __device__ static Half from(double v) { return Half{f16_bits(float(v))}; }
 };
 
+// ---- fused statistics -----------------------------------------------------------------
+// The emitted value as the caller receives it, widened to binary64.
+__device__ __forceinline__ double widen(float v) { return double(v); }
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ double widen(Bf16 v) { return double(__uint_as_float(uint32_t(v.u) << 16)); }
+__device__ __forceinline__ double widen(Half v) {
+  return double(float(__builtin_bit_cast(_Float16, v.u)));
+}
+
+constexpr uint32_t kHistSlots = kHistBins + 2;  // bins, then below -8 and at or above 8
+constexpr size_t kStatsLds = 16 * sizeof(double) + ((kHistSlots * 4 + 15) / 16) * 16;
+
+// Per-thread sums of y .. y^4 in emission order, and the workgroup's LDS
+// histogram: bin floor(256 y) + 2048 for y in [-8, 8) (256 y is exact).
+struct StatsAcc {
+  double m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
+  uint32_t *hist = nullptr;
+  __device__ __forceinline__ void add(double y) {
+    const double y2 = __dmul_rn(y, y);
+    m1 = __dadd_rn(m1, y);
+    m2 = __dadd_rn(m2, y2);
+    m3 = __dadd_rn(m3, __dmul_rn(y2, y));
+    m4 = __dadd_rn(m4, __dmul_rn(y2, y2));
+    const double z = __dmul_rn(y, 256.0);
+    uint32_t slot;
+    if (!(z >= -2048.0))
+      slot = kHistBins;
+    else if (z >= 2048.0)
+      slot = kHistBins + 1;
+    else
+      slot = uint32_t(int32_t(floor(z)) + 2048);
+    atomicAdd(hist + slot, 1u);
+  }
+};
+
 // ---- the per-workgroup pool engine ------------------------------------------------
 // SMALL: pools with L < 256, launched with BD = L threads and NQ = 1.
 // DB: two LDS pool buffers; a pass reads one and writes the other, so it needs
@@ -332,16 +367,24 @@ struct Engine {
     for (int m = 0; m < 4; ++m)
 #pragma unroll
       for (int c = 0; c < NQ; ++c) acc = sq_add(acc, y[c][m]);
+    return block_sum(acc, red);
+  }
+
+  // Balanced pairwise sum of one value per thread over the BD threads in
+  // thread order (lanes of a wave, then the waves), through 4 LDS slots.
+  // Ends with a barrier; every thread returns the same value.  Two calls on
+  // the same slots must be separated by a barrier.
+  __device__ __forceinline__ double block_sum(double acc, double *slots) const {
     const uint32_t B = bd();
     if (B >= 64) {
       acc = wave_pairwise_sum(acc);
     } else {
       for (uint32_t w = 1; w < B; w <<= 1) acc = __dadd_rn(acc, __shfl_xor(acc, int(w)));
     }
-    if (B > 64 && (tid & 63) == 0) red[tid >> 6] = acc;
+    if (B > 64 && (tid & 63) == 0) slots[tid >> 6] = acc;
     __syncthreads();
-    if (B == 128) return __dadd_rn(red[0], red[1]);
-    if (B == 256) return __dadd_rn(__dadd_rn(red[0], red[1]), __dadd_rn(red[2], red[3]));
+    if (B == 128) return __dadd_rn(slots[0], slots[1]);
+    if (B == 256) return __dadd_rn(__dadd_rn(slots[0], slots[1]), __dadd_rn(slots[2], slots[3]));
     return acc;
   }
 
@@ -356,10 +399,11 @@ struct Engine {
     }
   }
 
-  // Emit pool positions [lo, hi) scaled by fT to out[obase + (i - lo)].
-  template <bool NT, typename O>
+  // Emit pool positions [lo, hi) scaled by fT to out[obase + (i - lo)]; with
+  // STATS, also accumulate each emitted value into `sa`.
+  template <bool NT, bool STATS, typename O>
   __device__ __forceinline__ void emit(O *__restrict__ out, uint64_t obase, uint32_t lo,
-                                       uint32_t hi, T fT) const {
+                                       uint32_t hi, T fT, StatsAcc *sa) const {
     if (lo == 0 && hi == 4 * L - 1) {
       // a whole pool: every position but the withheld last one
       O *dst = out + obase + tid;
@@ -368,8 +412,10 @@ struct Engine {
 #pragma unroll
         for (int c = 0; c < NQ; ++c) {
           const O v = Cast<O>::from(T(y[c][m] * fT));
-          if (m < 3 || c < NQ - 1 || tid < bd() - 1)
+          if (m < 3 || c < NQ - 1 || tid < bd() - 1) {
             put<NT>(dst + (uint32_t(m) * L + uint32_t(c) * bd()), v);
+            if constexpr (STATS) sa->add(widen(v));
+          }
         }
       return;
     }
@@ -378,7 +424,11 @@ struct Engine {
 #pragma unroll
       for (int c = 0; c < NQ; ++c) {
         const uint32_t i = pos(m, c);
-        if (i >= lo && i < hi) put<NT>(out + (obase + (i - lo)), Cast<O>::from(T(y[c][m] * fT)));
+        if (i >= lo && i < hi) {
+          const O v = Cast<O>::from(T(y[c][m] * fT));
+          put<NT>(out + (obase + (i - lo)), v);
+          if constexpr (STATS) sa->add(widen(v));
+        }
       }
   }
 };
@@ -474,12 +524,52 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
 // the withheld value f * P[n-1] feeds the next sample.  The stored pool is
 // never scaled.  Starts and ends without a barrier of its own: the caller
 // separates two items on one workgroup by a barrier.
-template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT>
+// LDS of one workgroup: pool buffer(s), 4 partial-sum slots, and with
+// statistics 16 more slots and the histogram.
+template <typename T>
+__host__ __device__ constexpr size_t lds_bytes_for(uint32_t n, bool db, bool stats) {
+  return size_t(n) * sizeof(T) * (db ? 2 : 1) + 4 * sizeof(double) + (stats ? kStatsLds : 0);
+}
+
+__device__ __forceinline__ uint32_t *stats_hist(unsigned char *smem, size_t pool_bytes) {
+  return reinterpret_cast<uint32_t *>(smem + pool_bytes + 4 * sizeof(double) +
+                                      16 * sizeof(double));
+}
+
+__device__ __forceinline__ void hist_clear(uint32_t *hist) {
+  for (uint32_t b = threadIdx.x; b < kHistSlots; b += blockDim.x) hist[b] = 0u;
+}
+
+// Add the LDS histogram to the global one (integer adds: the result does not
+// depend on their order) and clear it.  Called by every thread after a barrier.
+__device__ __forceinline__ void hist_flush(uint32_t *hist, StatsOut *out) {
+  for (uint32_t b = threadIdx.x; b < kHistSlots; b += blockDim.x) {
+    const uint32_t v = hist[b];
+    if (v) {
+      unsigned long long *dst = b < kHistBins ? reinterpret_cast<unsigned long long *>(out->hist + b)
+                                : b == kHistBins ? reinterpret_cast<unsigned long long *>(&out->below)
+                                                 : reinterpret_cast<unsigned long long *>(&out->above);
+      atomicAdd(dst, (unsigned long long)v);
+      hist[b] = 0u;
+    }
+  }
+}
+
+template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, bool STATS = false>
 __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem, uint32_t s,
-                                          uint64_t count, uint64_t obase) {
+                                          uint64_t count, uint64_t obase, uint32_t req = 0) {
   StreamHdr *h = a.c.hdr + s;
   const uint32_t n = h->n;
   auto e = make_engine<T, NQ, SMALL, DB>(smem, n);
+  StatsAcc sa;
+  double t_sum = 0.0, t_sumsq = 0.0, t_lag = 0.0, tprev = 0.0;
+  uint64_t pools = 0, t_pairs = 0;
+  const uint64_t emitted = count;
+  if constexpr (STATS) {
+    sa.hist = stats_hist(smem, size_t(n) * sizeof(T) * (DB ? 2 : 1));
+    hist_clear(sa.hist);  // published by the barrier after the pool load
+    tprev = h->tprev;
+  }
   const Chi2Consts &cc = a.c.cc[__builtin_ctz(n) - 4];
   uint64_t xs = h->xs;
   uint64_t k = h->k;
@@ -495,7 +585,7 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
 
   if (cursor < n - 1) {
     const uint32_t take = take_of(count, n - 1 - cursor);
-    e.template emit<NT>(out, obase, cursor, cursor + take, T(f));
+    e.template emit<NT, STATS>(out, obase, cursor, cursor + take, T(f), &sa);
     obase += take;
     count -= take;
     cursor += take;
@@ -519,9 +609,23 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     f = fk;
     xnext = __dmul_rn(fk, last);
     qlast = Q;
+    if constexpr (STATS) {
+      // T = f^2 (Q - P[n-1]^2), the sum of squares of the pool's emitted
+      // values, centred on its expected value n - 1
+      const double Tk = __dsub_rn(__dmul_rn(__dmul_rn(fk, fk), __dsub_rn(Q, __dmul_rn(last, last))),
+                                  double(n - 1));
+      t_sum = __dadd_rn(t_sum, Tk);
+      t_sumsq = __dadd_rn(t_sumsq, __dmul_rn(Tk, Tk));
+      if (k > 0) {
+        t_lag = __dadd_rn(t_lag, __dmul_rn(Tk, tprev));
+        t_pairs += 1;
+      }
+      tprev = Tk;
+      pools += 1;
+    }
     k += 1;
     const uint32_t take = take_of(count, n - 1);
-    e.template emit<NT>(out, obase, 0, take, T(f));
+    e.template emit<NT, STATS>(out, obase, 0, take, T(f), &sa);
     obase += take;
     count -= take;
     cursor = take;
@@ -535,11 +639,36 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     h->xnext = xnext;
     h->qlast = qlast;
     h->cursor = cursor;
+    if constexpr (STATS) h->tprev = tprev;
+  }
+  if constexpr (STATS) {
+    // the request's moments: a pairwise tree over the threads, one slot set per
+    // moment; then the histogram goes to the global one
+    double *slots = e.red + 4;
+    const double s1 = e.block_sum(sa.m1, slots);
+    const double s2 = e.block_sum(sa.m2, slots + 4);
+    const double s3 = e.block_sum(sa.m3, slots + 8);
+    const double s4 = e.block_sum(sa.m4, slots + 12);
+    if (e.tid == 0) {
+      StatsPartial &pp = a.partials[req];
+      pp.moment[0] = s1;
+      pp.moment[1] = s2;
+      pp.moment[2] = s3;
+      pp.moment[3] = s4;
+      pp.t_sum = t_sum;
+      pp.t_sumsq = t_sumsq;
+      pp.t_lag = t_lag;
+      pp.count = emitted;
+      pp.pools = pools;
+      pp.t_pairs = t_pairs;
+    }
+    hist_flush(sa.hist, a.stats);
+    __syncthreads();  // slots and histogram are reused by the next item
   }
 }
 
 // One workgroup per work item (all items of the launch share one pool size).
-template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE>
+template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE, bool STATS = false>
 __global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t j = blockIdx.x;
@@ -555,15 +684,25 @@ __global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
     count = a.count_each;
     obase = uint64_t(j) * a.count_each;
   }
-  if (count == 0) return;
-  fill_item<T, O, NQ, SMALL, DB, NT>(a, smem, s, count, obase);
+  if (count == 0) {
+    if constexpr (STATS)
+      if (threadIdx.x == 0) a.partials[j] = StatsPartial{};
+    return;
+  }
+  const uint32_t req = a.items ? a.items[j].req : j;
+  fill_item<T, O, NQ, SMALL, DB, NT, STATS>(a, smem, s, count, obase, req);
+}
+
+template <typename T, typename O, int NQ, int MAXNQ, bool DB, bool NT, bool STATS>
+__device__ __forceinline__ void item_as(const FillArgs &a, unsigned char *smem, const WorkItem &it) {
+  fill_item<T, O, NQ, false, DB, NT, STATS>(a, smem, it.stream, it.count, it.out_off, it.req);
 }
 
 // Persistent form: a fixed grid of workgroups pops work items (pool sizes
 // 1024 .. 1024*MAXNQ, mixed) from a device counter in the order of the list
 // (the host sorts it longest first).  Every workgroup leaves the loop once the
 // counter passes the end of the list.
-template <typename T, typename O, int MAXNQ, bool DB, bool NT>
+template <typename T, typename O, int MAXNQ, bool DB, bool NT, bool STATS = false>
 __global__ __launch_bounds__(kBlock) void k_fill_persistent(FillArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t next_item;
@@ -574,21 +713,17 @@ __global__ __launch_bounds__(kBlock) void k_fill_persistent(FillArgs a) {
     const uint32_t j = next_item;
     if (j >= a.nitems) break;
     const WorkItem it = a.items[j];
-    if (it.count == 0) continue;
+    if (it.count == 0) {
+      if constexpr (STATS)
+        if (threadIdx.x == 0) a.partials[it.req] = StatsPartial{};
+      continue;
+    }
     switch (a.c.hdr[it.stream].n) {
-      case 1024: fill_item<T, O, 1, false, DB, NT>(a, smem, it.stream, it.count, it.out_off); break;
-      case 2048:
-        if constexpr (MAXNQ >= 2) fill_item<T, O, 2, false, DB, NT>(a, smem, it.stream, it.count, it.out_off);
-        break;
-      case 4096:
-        if constexpr (MAXNQ >= 4) fill_item<T, O, 4, false, DB, NT>(a, smem, it.stream, it.count, it.out_off);
-        break;
-      case 8192:
-        if constexpr (MAXNQ >= 8) fill_item<T, O, 8, false, DB, NT>(a, smem, it.stream, it.count, it.out_off);
-        break;
-      default:
-        if constexpr (MAXNQ >= 16) fill_item<T, O, 16, false, DB, NT>(a, smem, it.stream, it.count, it.out_off);
-        break;
+      case 1024: item_as<T, O, 1, MAXNQ, DB, NT, STATS>(a, smem, it); break;
+      case 2048: if constexpr (MAXNQ >= 2) item_as<T, O, 2, MAXNQ, DB, NT, STATS>(a, smem, it); break;
+      case 4096: if constexpr (MAXNQ >= 4) item_as<T, O, 4, MAXNQ, DB, NT, STATS>(a, smem, it); break;
+      case 8192: if constexpr (MAXNQ >= 8) item_as<T, O, 8, MAXNQ, DB, NT, STATS>(a, smem, it); break;
+      default: if constexpr (MAXNQ >= 16) item_as<T, O, 16, MAXNQ, DB, NT, STATS>(a, smem, it); break;
     }
   }
 }

@@ -18,7 +18,7 @@ struct StreamHdr {
   uint64_t pool_off;  // byte offset of the pool in the arena
   uint32_t n;         // pool size
   uint32_t cursor;    // next pool position to emit; n-1 = used up
-  uint32_t pad[2];
+  double tprev;       // centred emitted sum of squares of the current pool (statistics)
 };
 static_assert(sizeof(StreamHdr) == 64, "header must stay 64 bytes");
 
@@ -30,9 +30,31 @@ struct Chi2Consts {
 // One unit of work: a stream, how many values it emits, where they go.
 struct WorkItem {
   uint32_t stream;
-  uint32_t pad;
+  uint32_t req;      // index of the request (statistics partials are kept per request)
   uint64_t count;
   uint64_t out_off;  // element offset in the output
+};
+
+// Statistics of one request (fused statistics); reduced in request order.
+struct StatsPartial {
+  double moment[4];  // sums of y, y^2, y^3, y^4
+  double t_sum, t_sumsq, t_lag;
+  uint64_t count, pools, t_pairs;
+};
+static_assert(sizeof(StatsPartial) == 80, "partial layout");
+
+constexpr uint32_t kHistBins = 4096;  // floor(256 y) + 2048 for y in [-8, 8)
+
+// Device layout of wn_stats (include/wn.h).
+struct StatsOut {
+  uint64_t count;
+  double moment[4];
+  uint64_t below, above;
+  uint64_t pools;
+  double t_sum, t_sumsq;
+  uint64_t t_pairs;
+  double t_lag;
+  uint64_t hist[kHistBins];
 };
 
 enum : uint32_t { kChi2Cubic = 0, kChi2Off = 1, kChi2Fisher = 2, kChi2WH = 3 };
@@ -61,14 +83,23 @@ struct SeedArgs {
 
 struct FillArgs {
   KernelCommon c;
-  const WorkItem *items;  // device array, or null for the affine form below
-  uint32_t nitems;
-  uint32_t affine_s0;     // affine form: item j = (s0 + j, count_each, j * count_each)
-  uint64_t count_each;
-  void *out;
-  uint32_t variant;       // non-semantic kernel variant (bit 0: LDS double buffer, bit 1: NT stores)
-  uint32_t *counter;      // persistent form: next work item (reset by the launch)
+  const WorkItem *items = nullptr;  // device array, or null for the affine form below
+  uint32_t nitems = 0;
+  uint32_t affine_s0 = 0;           // affine form: item j = (s0 + j, count_each, j * count_each)
+  uint64_t count_each = 0;
+  void *out = nullptr;
+  uint32_t variant = 0;             // non-semantic kernel variant (wn_tuning)
+  uint32_t *counter = nullptr;      // persistent form: next work item (reset by the launch)
+  StatsPartial *partials = nullptr; // fused statistics: one partial per request, or null
+  StatsOut *stats = nullptr;        // fused statistics: histogram and tails accumulate here
 };
+
+// Fused statistics: zero `out` before a fill, and fold the request partials
+// into it (binary64 sums in a fixed order) after the fill.
+hipError_t stats_zero(StatsOut *out, hipStream_t s);
+hipError_t zero_words(void *p, uint32_t nwords, hipStream_t s);  // a kernel, not a memset
+hipError_t stats_reduce(const StatsPartial *partials, uint32_t nreq, StatsOut *out,
+                        hipStream_t s);
 
 // Launchers, one translation unit per pool type (wn_launch_f32.hip,
 // wn_launch_f64.hip).  Return hipSuccess or the launch error.

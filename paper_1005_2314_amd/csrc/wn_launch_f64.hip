@@ -8,7 +8,9 @@ namespace {
 
 using T = double;
 
-size_t lds_bytes(uint32_t n, bool db) { return size_t(n) * sizeof(T) * (db ? 2 : 1) + 4 * sizeof(double); }
+size_t lds_bytes(uint32_t n, bool db, bool stats = false) {
+  return lds_bytes_for<T>(n, db, stats);
+}
 
 template <typename Kern>
 hipError_t prepare(Kern kern, size_t lds) {
@@ -29,10 +31,10 @@ hipError_t seed_t(const SeedArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE = 1>
+template <typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE = 1, bool STATS = false>
 hipError_t fill_t(const FillArgs &a, hipStream_t st) {
-  const size_t lds = lds_bytes(a.c.n, DB);
-  auto kern = k_fill<T, O, NQ, SMALL, DB, NT, WPE>;
+  const size_t lds = lds_bytes(a.c.n, DB, STATS);
+  auto kern = k_fill<T, O, NQ, SMALL, DB, NT, WPE, STATS>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
   const uint32_t block = SMALL ? a.c.n / 4 : kBlock;
@@ -44,13 +46,14 @@ hipError_t fill_t(const FillArgs &a, hipStream_t st) {
 // bit 1 nontemporal output stores, bit 2 at most 64 VGPRs (8 waves per SIMD).
 template <typename O, int NQ>
 hipError_t fill_v(const FillArgs &a, hipStream_t st) {
+  if (a.partials) return fill_t<O, NQ, false, false, false, 1, true>(a, st);
   return fill_t<O, NQ, false, false, false>(a, st);
 }
 
-template <typename O, int MAXNQ, bool DB, bool NT>
+template <typename O, int MAXNQ, bool DB, bool NT, bool STATS = false>
 hipError_t persistent_t(const FillArgs &a, uint32_t grid, hipStream_t st) {
-  const size_t lds = lds_bytes(1024u * MAXNQ, DB);
-  auto kern = k_fill_persistent<T, O, MAXNQ, DB, NT>;
+  const size_t lds = lds_bytes(1024u * MAXNQ, DB, STATS);
+  auto kern = k_fill_persistent<T, O, MAXNQ, DB, NT, STATS>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
   if (grid == 0) {  // as many workgroups as can be resident at once
@@ -71,8 +74,9 @@ hipError_t persistent_t(const FillArgs &a, uint32_t grid, hipStream_t st) {
 
 template <typename O, int MAXNQ>
 hipError_t persistent_v(const FillArgs &a, uint32_t grid, hipStream_t st) {
+  if (a.partials) return persistent_t<O, MAXNQ, false, false, true>(a, grid, st);
   // two buffers only where they fit in the 160 KiB of LDS
-  if constexpr (2 * 1024 * MAXNQ * sizeof(T) + 4 * sizeof(double) <= kMaxLds)
+  if constexpr (lds_bytes_for<T>(1024 * MAXNQ, true, false) <= kMaxLds)
     if (a.variant & 1u) return persistent_t<O, MAXNQ, true, false>(a, grid, st);
   return persistent_t<O, MAXNQ, false, false>(a, grid, st);
 }
@@ -102,7 +106,9 @@ hipError_t fill_n(const FillArgs &a, hipStream_t st) {
     case 4096: return fill_v<O, 4>(a, st);
     case 8192: return fill_v<O, 8>(a, st);
     case 16384: return fill_v<O, 16>(a, st);
-    default: return fill_t<O, 1, true, false, false>(a, st);
+    default:
+      if (a.partials) return fill_t<O, 1, true, false, false, 1, true>(a, st);
+      return fill_t<O, 1, true, false, false>(a, st);
   }
 }
 

@@ -20,7 +20,8 @@ STATUS_NAMES = {0: "WN_OK", 1: "WN_EINVAL", 2: "WN_ENOMEM", 3: "WN_EDEVICE", 4: 
 
 # every symbol include/wn.h and include/wn_bench.h declare
 EXPORTED = ("wn_create", "wn_seed", "wn_fill", "wn_sync", "wn_get_stream", "wn_destroy",
-            "wn_last_error", "wn_version", "wn_set_tuning", "wn_get_tuning", "wn_autotune", "wn_bench_store", "wn_bench_traffic",
+            "wn_last_error", "wn_version", "wn_set_tuning", "wn_get_tuning", "wn_autotune",
+            "wn_fill_stats", "wn_bench_store", "wn_bench_traffic",
             "wn_bench_box_muller")
 
 
@@ -41,6 +42,16 @@ class wn_tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("lds_double_buffer", C.c_uint32),
                 ("nontemporal_stores", C.c_uint32), ("high_occupancy", C.c_uint32),
                 ("wgs_per_cu", C.c_uint32), ("use_graph", C.c_uint32)]
+
+
+HIST_BINS = 4096
+
+
+class wn_stats(C.Structure):
+    _fields_ = [("count", C.c_uint64), ("moment", C.c_double * 4), ("below", C.c_uint64),
+                ("above", C.c_uint64), ("pools", C.c_uint64), ("t_sum", C.c_double),
+                ("t_sumsq", C.c_double), ("t_pairs", C.c_uint64), ("t_lag", C.c_double),
+                ("hist", C.c_uint64 * HIST_BINS)]
 
 
 class WnError(RuntimeError):
@@ -84,6 +95,9 @@ def load():
         L.wn_autotune.argtypes = [vp, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
                                   vp, C.c_int, vp, C.POINTER(wn_tuning)]
         L.wn_autotune.restype = C.c_int
+        L.wn_fill_stats.argtypes = [vp, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
+                                    vp, C.c_int, vp, vp]
+        L.wn_fill_stats.restype = C.c_int
         L.wn_bench_store.argtypes = [vp, C.c_uint64, C.c_uint32, vp]
         L.wn_bench_store.restype = C.c_int
         L.wn_bench_traffic.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.c_uint64, vp]
@@ -234,6 +248,36 @@ class Generator:
 
     def sync(self):
         wn_sync(self._h)
+
+    def fill_stats_into(self, out, streams, counts, stats, stream=None):
+        """wn_fill_stats into a caller-owned CUDA output tensor; `stats` is a CUDA
+        uint8 tensor of sizeof(wn_stats) bytes (see read_stats)."""
+        import torch
+        dt = {torch.float64: WN_F64, torch.float32: WN_F32, torch.bfloat16: WN_BF16,
+              torch.float16: WN_F16}[out.dtype]
+        streams = np.ascontiguousarray(streams, np.uint32)
+        counts = np.ascontiguousarray(counts, np.uint64)
+        if stats.numel() * stats.element_size() < C.sizeof(wn_stats) or not stats.is_cuda:
+            raise ValueError("stats must be a CUDA buffer of sizeof(wn_stats) bytes")
+        check(load().wn_fill_stats(self._h, streams.size,
+                                   streams.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                   counts.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                   C.c_void_p(out.data_ptr()), dt,
+                                   C.c_void_p(stats.data_ptr()), self._stream_handle(stream)))
+        return out
+
+    @staticmethod
+    def stats_buffer(device=0):
+        import torch
+        return torch.zeros(C.sizeof(wn_stats), dtype=torch.uint8, device=f"cuda:{device}")
+
+    @staticmethod
+    def read_stats(buf):
+        """Copy a device stats buffer to a host wn_stats."""
+        host = buf.cpu().numpy()
+        st = wn_stats()
+        C.memmove(C.addressof(st), host.ctypes.data, C.sizeof(wn_stats))
+        return st
 
     def set_tuning(self, lds_double_buffer=None, nontemporal_stores=None, high_occupancy=None,
                    wgs_per_cu=None, use_graph=None):
