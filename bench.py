@@ -34,6 +34,29 @@ def parse():
     return ap.parse_args()
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_fill_batched_f32_hbm_traffic.md")
+FILL_SOURCES = [os.path.join(ROOT, "paper_1005_2314_amd", "csrc", f)
+                for f in ("wn_device.hpp", "wn_launch_f32.hip", "wn_internal.hpp")]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the generation kernel from the committed
+    FETCH_SIZE/WRITE_SIZE profile, or None when the kernel sources have changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        fields = dict(line.split(": ", 1) for line in open(TRAFFIC_PROFILE).read().splitlines()
+                      if ": " in line and line.split(": ", 1)[0].isidentifier())
+        h = hashlib.sha256()
+        for f in FILL_SOURCES:
+            h.update(open(f, "rb").read())
+        if h.hexdigest() != fields.get("source_sha256", "").strip():
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def workload_bytes(w, out_bytes_per_value):
     """Algorithmic HBM bytes of one fill: outputs written plus each stream's state
     (pool and 64-byte header) read once and written once."""
@@ -207,7 +230,7 @@ def main():
                    "streams": w["num_streams"], "per_stream": int(w["counts"][0]),
                    "pool_n": w["pool_n"], "passes": w["R"], "seed_ms": seed_s * 1e3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_fill<float,float,4>", "kernel_ms": avg_ms,
                      "bytes_per_launch": alg_bytes, "output_bytes": out_b,
                      "state_bytes": state_b,
