@@ -140,8 +140,8 @@ __device__ __forceinline__ double chi2_sample(const Chi2Consts &c, uint32_t mode
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
   const uint64_t u = uint64_t(__double_as_longlong(v));
-  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(u)), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(u >> 32)), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(int(uint32_t(u)), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(int(uint32_t(u >> 32)), CTRL, 0xF, 0xF, true);
   return __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
 }
 
@@ -222,6 +222,8 @@ __device__ __forceinline__ double widen(Half v) {
 
 constexpr uint32_t kHistSlots = kHistBins + 2;  // bins, then below -8 and at or above 8
 constexpr size_t kStatsLds = 16 * sizeof(double) + ((kHistSlots * 4 + 15) / 16) * 16;
+static_assert(((kHistSlots * 4 + 15) / 16) * 16 - kHistSlots * 4 >= 8,
+              "the histogram's padding holds the persistent kernel's item word");
 
 // Per-thread sums of y .. y^4 in emission order, and the workgroup's LDS
 // histogram: bin floor(256 y) + 2048 for y in [-8, 8) (256 y is exact).
@@ -257,35 +259,53 @@ struct StatsAcc {
 // second one rewrites the partial-sum slots the first one's readers use).
 template <typename T, int NQ, bool SMALL, bool DB>
 struct Engine {
-  T *cur;       // LDS buffer holding the pool
-  T *nxt;       // LDS buffer the next pass writes (== cur unless DB)
+  T *base;      // LDS: pool buffer 0, then buffer 1 when DB
   double *red;  // LDS, 4 partial sums
-  uint32_t L;
+  uint32_t Lr;  // row length for SMALL pools (else the compile-time kBlock * NQ)
   uint32_t tid;
-  T y[NQ][4];  // y[c][m] = element m*L + c*BD + tid
+  uint32_t cb;  // buffer holding the pool (0, or 1 when DB)
+  T y[NQ][4];   // y[c][m] = element m*L + c*BD + tid
 
-  __device__ __forceinline__ uint32_t bd() const { return SMALL ? L : kBlock; }
+  __device__ __forceinline__ uint32_t len() const { return SMALL ? Lr : kBlock * NQ; }
+  __device__ __forceinline__ uint32_t bd() const { return SMALL ? Lr : kBlock; }
+  __device__ __forceinline__ uint32_t pool_n() const { return 4 * len(); }
 
   __device__ __forceinline__ uint32_t pos(int m, int c) const {
-    return uint32_t(m) * L + uint32_t(c) * bd() + tid;
+    return uint32_t(m) * len() + uint32_t(c) * bd() + tid;
   }
 
+  // LDS buffer b (b is a compile-time constant wherever it matters, so the
+  // buffer offset can go into the LDS instruction's immediate field)
+  __device__ __forceinline__ T *buf(uint32_t b) const { return base + b * pool_n(); }
+
+  // The same buffer as a local-address-space pointer.  The kernels that use
+  // the engine have no static LDS, so dynamic LDS starts at local address 0
+  // (the build's device-assembly check enforces this), and the buffer's
+  // address is a constant: the gather needs no address add per access.
+  using LdsT = __attribute__((address_space(3))) const T;
+  __device__ __forceinline__ LdsT *lds_buf(uint32_t b) const {
+    return reinterpret_cast<LdsT *>(uintptr_t(b * pool_n() * uint32_t(sizeof(T))));
+  }
+  __device__ __forceinline__ T *cur() const { return DB ? buf(cb) : base; }
+
   __device__ __forceinline__ void load_global(const T *__restrict__ g) {
+    T *P = cur();
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
       for (int c = 0; c < NQ; ++c) {
         const T v = g[pos(m, c)];
         y[c][m] = v;
-        cur[pos(m, c)] = v;
+        P[pos(m, c)] = v;
       }
   }
 
   __device__ __forceinline__ void load_lds() {
+    const T *P = cur();
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int c = 0; c < NQ; ++c) y[c][m] = cur[pos(m, c)];
+      for (int c = 0; c < NQ; ++c) y[c][m] = P[pos(m, c)];
   }
 
   __device__ __forceinline__ void store_global(T *__restrict__ g) const {
@@ -297,10 +317,11 @@ struct Engine {
 
   // write the registers to the buffer holding the pool
   __device__ __forceinline__ void write_lds() {
+    T *P = cur();
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int c = 0; c < NQ; ++c) cur[pos(m, c)] = y[c][m];
+      for (int c = 0; c < NQ; ++c) P[pos(m, c)] = y[c][m];
   }
 
   // y <- T(double(y) * g)
@@ -311,17 +332,26 @@ struct Engine {
       for (int c = 0; c < NQ; ++c) y[c][m] = T(__dmul_rn(double(y[c][m]), g));
   }
 
-  template <int K>
+  // Gather quadruples from buffer RB and transform them with matrix K.  The
+  // row position is (alpha q + gamma) mod L for q = c*BD + tid: one add to
+  // step c and one mask per element; row and buffer offsets are immediates.
+  template <int K, int RB>
   __device__ __forceinline__ void gather_transform(const PassParams &p, bool renorm, double g) {
+    LdsT *P = lds_buf(RB);
+    const uint32_t L = len();
+    constexpr uint32_t W = sizeof(T);
+    const uint32_t mask = (L - 1) * W;  // byte offsets within a row
     T x[NQ][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const uint32_t a = p.alpha[m];
-      const uint32_t base = __umul24(a, tid) + p.gamma[m];
-      const uint32_t step = a * bd();
+      const uint32_t first = __umul24(a * W, tid) + p.gamma[m] * W;
+      const uint32_t step = a * bd() * W;
+      using LdsB = __attribute__((address_space(3))) const unsigned char;
+      LdsB *row = reinterpret_cast<LdsB *>(P + uint32_t(m) * L);
 #pragma unroll
       for (int c = 0; c < NQ; ++c)
-        x[c][m] = cur[uint32_t(m) * L + ((base + step * uint32_t(c)) & (L - 1))];
+        x[c][m] = *reinterpret_cast<LdsT *>(row + ((first + step * uint32_t(c)) & mask));
     }
     if (renorm) {
 #pragma unroll
@@ -333,29 +363,40 @@ struct Engine {
     for (int c = 0; c < NQ; ++c) quad<K>(x[c][0], x[c][1], x[c][2], x[c][3], y[c]);
   }
 
+  template <int RB>
+  __device__ __forceinline__ void pass_from(const PassParams &p, bool renorm, double g) {
+    constexpr int WB = DB ? 1 - RB : RB;
+    switch (p.k) {
+      case 0: gather_transform<0, RB>(p, renorm, g); break;
+      case 1: gather_transform<1, RB>(p, renorm, g); break;
+      case 2: gather_transform<2, RB>(p, renorm, g); break;
+      default: gather_transform<3, RB>(p, renorm, g); break;
+    }
+    if (!DB) __syncthreads();
+    T *W = buf(WB);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) W[pos(m, c)] = y[c][m];
+  }
+
   // One pass: gather from the LDS pool, transform, write the new pool.  The
   // caller places a barrier before the next read of the pool.  `renorm`
   // applies the renormalisation scale g to every gathered value first (each
   // element is gathered exactly once per pass, so this equals rescaling the
   // whole pool before the pass).
   __device__ __forceinline__ void pass(const PassParams &p, bool renorm, double g) {
-    switch (p.k) {
-      case 0: gather_transform<0>(p, renorm, g); break;
-      case 1: gather_transform<1>(p, renorm, g); break;
-      case 2: gather_transform<2>(p, renorm, g); break;
-      default: gather_transform<3>(p, renorm, g); break;
+    if (DB && cb != 0) {
+      pass_from<1>(p, renorm, g);
+    } else {
+      pass_from<0>(p, renorm, g);
     }
-    if (!DB) __syncthreads();
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int c = 0; c < NQ; ++c) nxt[pos(m, c)] = y[c][m];
-    if (DB) {
-      T *t = cur;
-      cur = nxt;
-      nxt = t;
-    }
+    if (DB) cb ^= 1u;
   }
+
+  // the pool's last element (the withheld one), after the barrier that
+  // published the pass writes
+  __device__ __forceinline__ T last() const { return cur()[pool_n() - 1]; }
 
   // Sum of squares of the pool held in y: running sum over this thread's
   // elements in increasing index order, then a balanced pairwise tree over
@@ -404,6 +445,7 @@ struct Engine {
   template <bool NT, bool STATS, typename O>
   __device__ __forceinline__ void emit(O *__restrict__ out, uint64_t obase, uint32_t lo,
                                        uint32_t hi, T fT, StatsAcc *sa) const {
+    const uint32_t L = len();
     if (lo == 0 && hi == 4 * L - 1) {
       // a whole pool: every position but the withheld last one
       O *dst = out + obase + tid;
@@ -436,11 +478,11 @@ struct Engine {
 template <typename T, int NQ, bool SMALL, bool DB>
 __device__ __forceinline__ Engine<T, NQ, SMALL, DB> make_engine(unsigned char *smem, uint32_t n) {
   Engine<T, NQ, SMALL, DB> e;
-  e.cur = reinterpret_cast<T *>(smem);
-  e.nxt = DB ? e.cur + n : e.cur;
+  e.base = reinterpret_cast<T *>(smem);
   e.red = reinterpret_cast<double *>(smem + size_t(n) * sizeof(T) * (DB ? 2 : 1));
-  e.L = n / 4;
+  e.Lr = n / 4;
   e.tid = threadIdx.x;
+  e.cb = 0;
   return e;
 }
 
@@ -458,14 +500,55 @@ __device__ __forceinline__ void flag_fault(uint32_t *err, double Q) {
   if (!(Q > 0.0) || !(Q < __builtin_huge_val())) atomicOr(err, 1u);
 }
 
+// ---- LDS layout ---------------------------------------------------------------------
+// LDS of one workgroup (all dynamic, from local address 0): pool buffer(s),
+// 4 partial-sum slots, 2 words for broadcasts, and with statistics 16 more
+// slots and the histogram.
+constexpr size_t kMiscLds = 2 * sizeof(uint64_t);
+
+template <typename T>
+__host__ __device__ constexpr size_t lds_bytes_for(uint32_t n, bool db, bool stats) {
+  return size_t(n) * sizeof(T) * (db ? 2 : 1) + 4 * sizeof(double) + kMiscLds +
+         (stats ? kStatsLds : 0);
+}
+
+// broadcast word w (0 or 1) after the partial-sum slots
+__device__ __forceinline__ uint64_t *misc_word(unsigned char *smem, size_t pool_bytes, int w) {
+  return reinterpret_cast<uint64_t *>(smem + pool_bytes + 4 * sizeof(double)) + w;
+}
+
+__device__ __forceinline__ uint32_t *stats_hist(unsigned char *smem, size_t pool_bytes) {
+  return reinterpret_cast<uint32_t *>(smem + pool_bytes + 4 * sizeof(double) + kMiscLds +
+                                      16 * sizeof(double));
+}
+
+__device__ __forceinline__ void hist_clear(uint32_t *hist) {
+  for (uint32_t b = threadIdx.x; b < kHistSlots; b += blockDim.x) hist[b] = 0u;
+}
+
+// Add the LDS histogram to the global one (integer adds: the result does not
+// depend on their order) and clear it.  Called by every thread after a barrier.
+__device__ __forceinline__ void hist_flush(uint32_t *hist, StatsOut *out) {
+  for (uint32_t b = threadIdx.x; b < kHistSlots; b += blockDim.x) {
+    const uint32_t v = hist[b];
+    if (v) {
+      unsigned long long *dst = b < kHistBins ? reinterpret_cast<unsigned long long *>(out->hist + b)
+                                : b == kHistBins ? reinterpret_cast<unsigned long long *>(&out->below)
+                                                 : reinterpret_cast<unsigned long long *>(&out->above);
+      atomicAdd(dst, (unsigned long long)v);
+      hist[b] = 0u;
+    }
+  }
+}
+
 // ---- seeding (Section 5.8: the uniform source initialises the pool) ----------------
 template <typename T, int NQ, bool SMALL>
 __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint64_t xs_shared;
   const uint32_t s = a.streams[blockIdx.x];
   const uint32_t n = a.c.n;
   auto e = make_engine<T, NQ, SMALL, false>(smem, n);
+  uint64_t &xs_shared = *misc_word(smem, size_t(n) * sizeof(T), 0);
   StreamHdr *h = a.c.hdr + s;
 
   // Initial values from the top 23 bits of successive uniforms:
@@ -475,7 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
     for (uint32_t i = 0; i < n; ++i) {
       const uint64_t v = xs_next(xs);
       const double c = __dadd_rn(double(int64_t(v >> 41) - (int64_t(1) << 22)), 0.5);
-      e.cur[i] = T(__dmul_rn(c, 0x1p-22));
+      e.cur()[i] = T(__dmul_rn(c, 0x1p-22));
     }
     xs_shared = xs;
   }
@@ -491,7 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
   for (uint32_t w = 0; w < a.warmup; ++w) {
     const uint64_t u1 = xs_next(xs);
     const uint64_t u2 = xs_next(xs);
-    e.pass(decode(u1, u2, e.L), false, 1.0);
+    e.pass(decode(u1, u2, e.len()), false, 1.0);
     __syncthreads();
   }
   Q = e.sumsq();
@@ -500,7 +583,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
   __syncthreads();
   Q = e.sumsq();
   if (e.tid == 0) flag_fault(a.c.err, Q);
-  const double last = double(e.cur[n - 1]);
+  const double last = double(e.last());
 
   e.store_global(reinterpret_cast<T *>(a.c.arena + h->pool_off));
   if (e.tid == 0) {
@@ -524,37 +607,6 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
 // the withheld value f * P[n-1] feeds the next sample.  The stored pool is
 // never scaled.  Starts and ends without a barrier of its own: the caller
 // separates two items on one workgroup by a barrier.
-// LDS of one workgroup: pool buffer(s), 4 partial-sum slots, and with
-// statistics 16 more slots and the histogram.
-template <typename T>
-__host__ __device__ constexpr size_t lds_bytes_for(uint32_t n, bool db, bool stats) {
-  return size_t(n) * sizeof(T) * (db ? 2 : 1) + 4 * sizeof(double) + (stats ? kStatsLds : 0);
-}
-
-__device__ __forceinline__ uint32_t *stats_hist(unsigned char *smem, size_t pool_bytes) {
-  return reinterpret_cast<uint32_t *>(smem + pool_bytes + 4 * sizeof(double) +
-                                      16 * sizeof(double));
-}
-
-__device__ __forceinline__ void hist_clear(uint32_t *hist) {
-  for (uint32_t b = threadIdx.x; b < kHistSlots; b += blockDim.x) hist[b] = 0u;
-}
-
-// Add the LDS histogram to the global one (integer adds: the result does not
-// depend on their order) and clear it.  Called by every thread after a barrier.
-__device__ __forceinline__ void hist_flush(uint32_t *hist, StatsOut *out) {
-  for (uint32_t b = threadIdx.x; b < kHistSlots; b += blockDim.x) {
-    const uint32_t v = hist[b];
-    if (v) {
-      unsigned long long *dst = b < kHistBins ? reinterpret_cast<unsigned long long *>(out->hist + b)
-                                : b == kHistBins ? reinterpret_cast<unsigned long long *>(&out->below)
-                                                 : reinterpret_cast<unsigned long long *>(&out->above);
-      atomicAdd(dst, (unsigned long long)v);
-      hist[b] = 0u;
-    }
-  }
-}
-
 template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, bool STATS = false>
 __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem, uint32_t s,
                                           uint64_t count, uint64_t obase, uint32_t req = 0) {
@@ -598,11 +650,11 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     for (uint32_t r = 0; r < a.c.R; ++r) {
       const uint64_t u1 = xs_next(xs);
       const uint64_t u2 = xs_next(xs);
-      e.pass(decode(u1, u2, e.L), renorm && r == 0, g);
+      e.pass(decode(u1, u2, e.len()), renorm && r == 0, g);
       if (r + 1 < a.c.R) __syncthreads();
     }
     const double Q = e.sumsq();
-    const double last = double(e.cur[n - 1]);
+    const double last = double(e.last());
     double fk = 1.0;
     if (a.c.chi2 != kChi2Off) fk = __dsqrt_rn(__ddiv_rn(chi2_sample(cc, a.c.chi2, xnext), Q));
     if (e.tid == 0) flag_fault(a.c.err, Q);
@@ -644,7 +696,7 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   if constexpr (STATS) {
     // the request's moments: a pairwise tree over the threads, one slot set per
     // moment; then the histogram goes to the global one
-    double *slots = e.red + 4;
+    double *slots = e.red + 4 + kMiscLds / sizeof(double);
     const double s1 = e.block_sum(sa.m1, slots);
     const double s2 = e.block_sum(sa.m2, slots + 4);
     const double s3 = e.block_sum(sa.m3, slots + 8);
@@ -705,12 +757,15 @@ __device__ __forceinline__ void item_as(const FillArgs &a, unsigned char *smem, 
 template <typename T, typename O, int MAXNQ, bool DB, bool NT, bool STATS = false>
 __global__ __launch_bounds__(kBlock) void k_fill_persistent(FillArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t next_item;
+  // the last 8 bytes of the allocation: the largest pool's spare broadcast
+  // word (or the histogram's padding); no item's layout reaches them
+  uint64_t &next_item = *reinterpret_cast<uint64_t *>(
+      smem + lds_bytes_for<T>(1024 * MAXNQ, DB, STATS) - sizeof(uint64_t));
   for (;;) {
     __syncthreads();  // the previous item's last LDS reads are done
     if (threadIdx.x == 0) next_item = atomicAdd(a.counter, 1u);
     __syncthreads();
-    const uint32_t j = next_item;
+    const uint32_t j = uint32_t(next_item);
     if (j >= a.nitems) break;
     const WorkItem it = a.items[j];
     if (it.count == 0) {

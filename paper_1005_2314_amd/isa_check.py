@@ -1,4 +1,6 @@
-"""Guard against a gfx950 code-generation fault seen with this library.
+"""Checks of the library's device assembly (run by the CPU tests).
+
+1. Guard against a gfx950 code-generation fault seen with this library.
 
 A wave-uniform 64-bit unsigned compare feeding a select was emitted as a VALU
 compare into VCC followed by s_cselect, which reads SCC; SCC then held the
@@ -6,6 +8,9 @@ side effect of an exec-mask restore.  The kernels avoid the construct
 (take_of() in wn_device.hpp); this check reads the device assembly the build
 keeps and reports any s_cselect/s_cmov whose SCC can only come from an
 exec-mask operation while a VALU compare into VCC sits in between.
+
+2. The generator kernels must have no static LDS: the pool engine addresses
+its LDS buffers as constants from local address 0.
 """
 import os
 import re
@@ -54,8 +59,30 @@ def stale_scc_selects(asm: str):
     return found
 
 
+_KERNEL = re.compile(r"^\s+\.amdhsa_kernel\s+(\S+)")
+_STATIC_LDS = re.compile(r"^\s+\.amdhsa_group_segment_fixed_size\s+(\d+)")
+
+
+def static_lds_of_engine_kernels(asm: str):
+    """(kernel, bytes) for every generator kernel that declares static LDS; the
+    pool engine addresses LDS from local address 0, which holds only when a
+    kernel's LDS is all dynamic."""
+    found = []
+    kernel = None
+    for line in asm.split("\n"):
+        m = _KERNEL.match(line)
+        if m:
+            kernel = m.group(1)
+            continue
+        m = _STATIC_LDS.match(line)
+        if m and kernel and any(k in kernel for k in ("k_fill", "k_seed")) and int(m.group(1)):
+            found.append((kernel, int(m.group(1))))
+    return found
+
+
 def check_library_sources():
     bad = []
     for name, asm in device_asm_texts().items():
         bad += [(name, k, ln) for k, ln in stale_scc_selects(asm)]
+        bad += [(name, k, f"static LDS {b}") for k, b in static_lds_of_engine_kernels(asm)]
     return bad

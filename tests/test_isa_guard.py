@@ -20,3 +20,12 @@ def test_checker_flags_the_known_bad_sequence():
 
 def test_library_device_code_has_no_stale_scc_select():
     assert isa_check.check_library_sources() == []
+
+
+def test_static_lds_checker():
+    asm = """	.amdhsa_kernel _Z6k_fillv
+		.amdhsa_group_segment_fixed_size 16
+	.amdhsa_kernel _Z6k_sumv
+		.amdhsa_group_segment_fixed_size 64
+"""
+    assert isa_check.static_lds_of_engine_kernels(asm) == [("_Z6k_fillv", 16)]
