@@ -82,8 +82,8 @@ typedef struct {
   uint32_t struct_size;        /* sizeof(wn_tuning) */
   uint32_t lds_double_buffer;  /* 1: two LDS pool buffers, one barrier per pass */
   uint32_t nontemporal_stores; /* 1: output stores bypass cache retention */
-  uint32_t high_occupancy;     /* 1: cap registers for 8 waves per SIMD (not with nontemporal;
-                                  one-size launches only) */
+  uint32_t waves_per_simd;     /* 0, or 5, 6 or 8: cap registers so that this many waves fit
+                                  per SIMD (not with nontemporal; one-size launches only) */
   uint32_t wgs_per_cu;         /* persistent launches: workgroups per compute unit
                                   (0 = as many as can be resident), <= 16 */
   uint32_t use_graph;          /* 1: persistent launches replay a captured HIP graph */
@@ -151,8 +151,9 @@ wn_status wn_sync(wn_gen *g);
 wn_status wn_get_stream(wn_gen *g, uint32_t s, wn_stream_info *info, void *pool_out);
 
 /* Set or read the generator's launch choices.  wn_set_tuning validates the
- * struct (WN_EINVAL on a bad size, a flag other than 0/1, high_occupancy with
- * nontemporal_stores, or wgs_per_cu > 16) and applies to later calls.  Binary32 pools of
+ * struct (WN_EINVAL on a bad size, a flag other than 0/1, waves_per_simd other
+ * than 0/5/6/8 or set with nontemporal_stores, or wgs_per_cu > 16) and applies
+ * to later calls.  Binary32 pools of
  * 1024..8192 values have every choice; other shapes ignore them.  Defaults:
  * the choices measured fastest for binary32 pools on MI355X. */
 wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t);

@@ -716,11 +716,13 @@ wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t) {
   if (t->struct_size != sizeof(wn_tuning))
     return fail(WN_EINVAL, "wn_set_tuning: struct_size %u, expected %zu", t->struct_size,
                 sizeof(wn_tuning));
-  if (t->lds_double_buffer > 1 || t->nontemporal_stores > 1 || t->high_occupancy > 1 ||
-      t->use_graph > 1 || (t->high_occupancy && t->nontemporal_stores) || t->wgs_per_cu > 16)
-    return fail(WN_EINVAL, "wn_set_tuning: flags must be 0 or 1 (high_occupancy without "
-                           "nontemporal_stores), wgs_per_cu <= 16");
-  g->variant = t->lds_double_buffer | (t->nontemporal_stores << 1) | (t->high_occupancy << 2);
+  const uint32_t w = t->waves_per_simd;
+  const uint32_t wcode = w == 0 ? 0u : w == 8 ? 1u : w == 6 ? 2u : w == 5 ? 3u : 4u;
+  if (t->lds_double_buffer > 1 || t->nontemporal_stores > 1 || wcode > 3 || t->use_graph > 1 ||
+      (wcode && t->nontemporal_stores) || t->wgs_per_cu > 16)
+    return fail(WN_EINVAL, "wn_set_tuning: flags must be 0 or 1, waves_per_simd 0/5/6/8 and "
+                           "not with nontemporal_stores, wgs_per_cu <= 16");
+  g->variant = t->lds_double_buffer | (t->nontemporal_stores << 1) | (wcode << 2);
   g->wgs_per_cu = t->wgs_per_cu;
   g->use_graph = t->use_graph != 0;
   return WN_OK;
@@ -731,7 +733,8 @@ wn_status wn_get_tuning(wn_gen *g, wn_tuning *t) {
   t->struct_size = sizeof(wn_tuning);
   t->lds_double_buffer = g->variant & 1u;
   t->nontemporal_stores = (g->variant >> 1) & 1u;
-  t->high_occupancy = (g->variant >> 2) & 1u;
+  static const uint32_t kWaves[4] = {0u, 8u, 6u, 5u};
+  t->waves_per_simd = kWaves[(g->variant >> 2) & 3u];
   t->wgs_per_cu = g->wgs_per_cu;
   t->use_graph = g->use_graph ? 1u : 0u;
   return WN_OK;
@@ -764,13 +767,13 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
     wn_tuning t = cur;
     t.lds_double_buffer = db;
     t.nontemporal_stores = nt;
-    t.high_occupancy = oc;
+    t.waves_per_simd = oc;
     t.wgs_per_cu = wpc;
     cands.push_back(t);
   };
   if (affine) {
     for (uint32_t db = 0; db < 2; ++db)
-      for (uint32_t oc = 0; oc < 2; ++oc) add(db, 0, oc, cur.wgs_per_cu);
+      for (uint32_t wps : {0u, 5u, 6u, 8u}) add(db, 0, wps, cur.wgs_per_cu);
     add(1, 1, 0, cur.wgs_per_cu);
   } else {
     for (uint32_t db = 0; db < 2; ++db)

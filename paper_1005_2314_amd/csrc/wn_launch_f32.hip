@@ -43,7 +43,8 @@ hipError_t fill_t(const FillArgs &a, hipStream_t st) {
 }
 
 // Non-semantic variants (identical results): bit 0 double-buffered LDS,
-// bit 1 nontemporal output stores, bit 2 at most 64 VGPRs (8 waves per SIMD).
+// bit 1 nontemporal output stores (with bit 0), bits 2-3 a register cap for
+// 8, 6 or 5 waves per SIMD.
 template <typename O, int NQ>
 hipError_t fill_v(const FillArgs &a, hipStream_t st) {
   if (a.partials) {  // fused statistics: one variant (two LDS buffers where they fit)
@@ -51,14 +52,18 @@ hipError_t fill_v(const FillArgs &a, hipStream_t st) {
     return fill_t<O, NQ, false, false, false, 1, true>(a, st);
   }
   if constexpr (NQ <= 8) {
-    switch (a.variant & 7u) {
-      case 1: return fill_t<O, NQ, false, true, false>(a, st);
-      case 2:
-      case 3: return fill_t<O, NQ, false, true, true>(a, st);
-      case 4: return fill_t<O, NQ, false, false, false, 8>(a, st);
-      case 5: return fill_t<O, NQ, false, true, false, 8>(a, st);
+    const bool db = a.variant & 1u;
+    switch ((a.variant >> 2) & 3u) {  // waves-per-SIMD cap: none, 8, 6, 5
+      case 1: return db ? fill_t<O, NQ, false, true, false, 8>(a, st)
+                        : fill_t<O, NQ, false, false, false, 8>(a, st);
+      case 2: return db ? fill_t<O, NQ, false, true, false, 6>(a, st)
+                        : fill_t<O, NQ, false, false, false, 6>(a, st);
+      case 3: return db ? fill_t<O, NQ, false, true, false, 5>(a, st)
+                        : fill_t<O, NQ, false, false, false, 5>(a, st);
       default: break;
     }
+    if (a.variant & 2u) return fill_t<O, NQ, false, true, true>(a, st);
+    if (db) return fill_t<O, NQ, false, true, false>(a, st);
   }
   return fill_t<O, NQ, false, false, false>(a, st);
 }

@@ -62,8 +62,13 @@ def batched(W, inputs, stream):
     torch.cuda.synchronize()
     seed_ms = (time.perf_counter() - t0) * 1e3
     out = torch.empty(int(w["counts"].sum()), dtype=torch.float32, device="cuda")
+    ms_default = _time(lambda: g.fill_into(out, w["streams"], w["counts"], stream), stream, reps=5)
+    t = g.autotune(out, w["streams"], w["counts"], stream)
     ms = _time(lambda: g.fill_into(out, w["streams"], w["counts"], stream), stream, reps=5)
-    res = {"ms": ms, "normals_per_s": out.numel() / ms * 1e3, "seed_ms": seed_ms}
+    res = {"ms": ms, "normals_per_s": out.numel() / ms * 1e3, "seed_ms": seed_ms,
+           "ms_default_tuning": ms_default,
+           "tuning": {"lds_double_buffer": t.lds_double_buffer,
+                      "waves_per_simd": t.waves_per_simd}}
     for dt, name in ((W.WN_BF16, "bf16"), (W.WN_F16, "f16")):
         o16 = torch.empty(out.numel(), dtype=W.torch_dtype(dt), device="cuda")
         m = _time(lambda: g.fill_into(o16, w["streams"], w["counts"], stream), stream, reps=5)

@@ -40,7 +40,7 @@ class wn_stream_info(C.Structure):
 
 class wn_tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("lds_double_buffer", C.c_uint32),
-                ("nontemporal_stores", C.c_uint32), ("high_occupancy", C.c_uint32),
+                ("nontemporal_stores", C.c_uint32), ("waves_per_simd", C.c_uint32),
                 ("wgs_per_cu", C.c_uint32), ("use_graph", C.c_uint32)]
 
 
@@ -279,7 +279,7 @@ class Generator:
         C.memmove(C.addressof(st), host.ctypes.data, C.sizeof(wn_stats))
         return st
 
-    def set_tuning(self, lds_double_buffer=None, nontemporal_stores=None, high_occupancy=None,
+    def set_tuning(self, lds_double_buffer=None, nontemporal_stores=None, waves_per_simd=None,
                    wgs_per_cu=None, use_graph=None):
         t = self.tuning()
         if wgs_per_cu is not None:
@@ -290,8 +290,8 @@ class Generator:
             t.lds_double_buffer = int(lds_double_buffer)
         if nontemporal_stores is not None:
             t.nontemporal_stores = int(nontemporal_stores)
-        if high_occupancy is not None:
-            t.high_occupancy = int(high_occupancy)
+        if waves_per_simd is not None:
+            t.waves_per_simd = int(waves_per_simd)
         check(load().wn_set_tuning(self._h, C.byref(t)))
 
     def tuning(self):

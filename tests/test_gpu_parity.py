@@ -163,16 +163,16 @@ def test_two_streams_ordering():
     assert_bits_equal(to_numpy_bits(b), ob, "second stream")
 
 
-@pytest.mark.parametrize("db,nt,oc", [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1),
-                                      (1, 0, 1)])
+@pytest.mark.parametrize("db,nt,oc", [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 8),
+                                      (1, 0, 8), (0, 0, 6), (1, 0, 5)])
 @pytest.mark.parametrize("n,out", [(1024, W.WN_F32), (2048, W.WN_BF16), (4096, W.WN_F32),
                                    (4096, W.WN_F16), (8192, W.WN_F32)])
 def test_tuning_variants_bit_exact(db, nt, oc, n, out):
     ns = 5
     p = Pair(ns, pool_n=n, R=2, seed=31, K=3)
-    p.gpu.set_tuning(lds_double_buffer=db, nontemporal_stores=nt, high_occupancy=oc)
+    p.gpu.set_tuning(lds_double_buffer=db, nontemporal_stores=nt, waves_per_simd=oc)
     t = p.gpu.tuning()
-    assert (t.lds_double_buffer, t.nontemporal_stores, t.high_occupancy) == (db, nt, oc)
+    assert (t.lds_double_buffer, t.nontemporal_stores, t.waves_per_simd) == (db, nt, oc)
     g, o = p.fill(np.arange(ns), [4 * (n - 1) + 5] * ns, out)
     assert_bits_equal(g, o, "affine")
     g, o = p.fill([3, 1, 4], [n + 7, 2 * n, 1], out)
