@@ -51,8 +51,25 @@ typedef enum { WN_F64 = 0, WN_F32 = 1, WN_BF16 = 2, WN_F16 = 3 } wn_dtype;
  * is 2 chi2 ~ (x + sqrt(2 nu - 1))^2; WH is the Wilson-Hilferty cube. */
 typedef enum { WN_CHI2_CUBIC = 0, WN_CHI2_OFF = 1, WN_CHI2_FISHER = 2, WN_CHI2_WH = 3 } wn_chi2;
 
+/* Where the chi-square sample of pool k takes its normal deviate x (Section
+ * 5.5): PREVIOUS is the withheld, scaled last value of pool k-1 (fastnorm2,
+ * the default); CURRENT is the last value of pool k itself (fastnorm's choice,
+ * which couples the scale to the emitted sum of squares; kept as a control). */
+typedef enum { WN_X_PREVIOUS = 0, WN_X_CURRENT = 1 } wn_chi2_source;
+
+/* The orthogonal transform of a pass.  A4: the 4x4 matrices A1 D_k of
+ * Section 5.3 (seven additions, one halving).  ROTATION: plane rotations
+ * R(theta) with cos = (1-t^2)/(1+t^2), sin = 2t/(1+t^2) and t fixed per pass
+ * (Section 5.3, the rann4 form).  A rotation pass treats the pool as two
+ * rows of n/2, reads row r through q -> (alpha_r q + gamma_r) mod n/2 with odd
+ * alpha_r (Section 5.4), draws t in [0, 1) from 24 bits and random signs for
+ * cos and sin (Section 5.2), and writes (c a + s b, c b - s a) to position q
+ * of the two rows.  Seeding runs 2 log2(n) + 4 warm-up passes instead of
+ * log2(n) + 4: a pair-join grows dependency sets half as fast. */
+typedef enum { WN_TRANSFORM_A4 = 0, WN_TRANSFORM_ROTATION = 1 } wn_transform;
+
 typedef struct {
-  uint32_t struct_size;       /* sizeof(wn_config), for ABI versioning */
+  uint32_t struct_size;       /* sizeof(wn_config), or WN_CONFIG_V1_SIZE (fields up to device) */
   uint32_t num_streams;       /* >= 1; stream ids are 0 .. num_streams-1 */
   const uint32_t *pool_n;     /* host array [num_streams] of pool sizes, or NULL */
   uint32_t default_pool_n;    /* pool size when pool_n == NULL */
@@ -61,9 +78,19 @@ typedef struct {
   wn_chi2 chi2;               /* rescale mode */
   uint32_t renorm_period;     /* K: renormalise every K pools (0 = never) */
   int device;                 /* HIP device ordinal */
+  /* version 2 */
+  wn_chi2_source chi2_source; /* default WN_X_PREVIOUS */
+  wn_transform transform;     /* default WN_TRANSFORM_A4 */
+  double mean;                /* mu added to every output (0: none) */
+  double stddev;              /* sigma > 0 folded into the scale (1: none) */
 } wn_config;
+#define WN_CONFIG_V1_SIZE 40u
 /* Pool sizes are powers of two in [16, 16384].  The library copies the
- * configuration (and pool_n) during wn_create. */
+ * configuration (and pool_n) during wn_create.  A version-1 struct (size
+ * WN_CONFIG_V1_SIZE) gets the version-2 defaults.  With mean mu and stddev
+ * sigma, value i of pool k is T(P[i] * T(f_k * sigma)), plus T(mu) in the pool
+ * type when mu != 0 (Section 5.5: sigma costs nothing, being folded into the
+ * scale); sigma = 1, mu = 0 leave the generator's bits unchanged. */
 
 /* Per-stream state as returned by wn_get_stream. */
 typedef struct {
@@ -131,7 +158,20 @@ typedef struct {
   uint64_t t_pairs;      /* pools produced that have a predecessor in their stream */
   double t_lag;          /* sum of D_k * D_{k-1} over those pools */
   uint64_t hist[4096];   /* count of values with floor(256 y) + 2048 = bin, y in [-8, 8) */
+  /* Adjacent-pool clustering of rare values (Section 5.7).  A pool holds an
+   * extreme value when one of its n-1 emitted positions has
+   * |T(P[i] T(f))| >= c_n (the standardised value in the pool type, before
+   * mean and stddev; c_n from wn_extreme_threshold).  Under independence
+   * x_pairs / t_pairs is about (x_pools / pools)^2; a finite pool makes it
+   * larger, less so with more passes per emitted pool. */
+  uint64_t x_pools;      /* pools produced that hold an extreme value */
+  uint64_t x_pairs;      /* of the t_pairs pools, those that hold one after a pool that did */
 } wn_stats;
+
+/* The extreme-value threshold c_n of wn_stats for pools of n values: the
+ * smallest multiple of 2^-8 with erfc(c_n / sqrt 2) <= 0.1 / n, so that about
+ * one pool in ten holds such a value.  Host only; NaN for an unsupported n. */
+double wn_extreme_threshold(uint32_t n);
 
 /* wn_fill plus fused statistics of the emitted values into `stats`
  * (caller-owned device memory, 8-byte aligned, sizeof(wn_stats); overwritten).
@@ -169,6 +209,18 @@ wn_status wn_get_tuning(wn_gen *g, wn_tuning *t);
  * Errors: as wn_fill, plus WN_ENOMEM. */
 wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
                       void *out, wn_dtype out_dtype, void *hip_stream, wn_tuning *best);
+
+/* Checkpoints: the complete state of every stream (pools, uniform states,
+ * scales, cursors) as a host byte buffer of wn_state_size(g) bytes.
+ * wn_save_state copies it out after the generator's queued work; wn_load_state
+ * restores it (the generator must have the same configuration; it counts as
+ * seeded afterwards).  Restoring a saved state and repeating the same calls
+ * reproduces their outputs bit for bit.  Both are synchronous.
+ * Errors: WN_EINVAL (NULL buffer, wrong size, or a state saved under another
+ * configuration), WN_ESTATE (save before seed), WN_EDEVICE. */
+size_t wn_state_size(const wn_gen *g);
+wn_status wn_save_state(wn_gen *g, void *host_buf, size_t bytes);
+wn_status wn_load_state(wn_gen *g, const void *host_buf, size_t bytes);
 
 /* Free everything the generator owns.  NULL-safe.  Waits for its work. */
 void wn_destroy(wn_gen *g);

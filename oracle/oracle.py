@@ -20,7 +20,7 @@ _OUT_NP = {F64: np.float64, F32: np.float32, BF16: np.uint16, F16: np.uint16}
 class _Config(C.Structure):
     _fields_ = [(name, C.c_uint32) for name in (
         "num_streams", "default_pool_n", "R", "pool_f64", "chi2", "K", "hazard", "warmup",
-        "trace")]
+        "trace", "x_current", "transform", "pad")] + [("mean", C.c_double), ("stddev", C.c_double)]
 
 
 class StreamInfo(C.Structure):
@@ -52,6 +52,13 @@ def lib():
         L.orc_pass_f32.argtypes = [f32p, C.c_uint32, C.c_int32, u32p, u32p, C.c_uint32]
         L.orc_pass_f64.argtypes = [f64p, C.c_uint32, C.c_int32, u32p, u32p, C.c_uint32]
         L.orc_transform_f64.argtypes = [f64p, C.c_int32, f64p]
+        L.orc_decode_rotation.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, u32p, u32p, f64p]
+        L.orc_rotation_pass_f32.argtypes = [f32p, C.c_uint32, u32p, u32p, C.c_double,
+                                            C.c_double]
+        L.orc_rotation_pass_f64.argtypes = [f64p, C.c_uint32, u32p, u32p, C.c_double,
+                                            C.c_double]
+        L.orc_warmup_passes.argtypes = [C.c_uint32, C.c_uint32]
+        L.orc_warmup_passes.restype = C.c_uint32
         L.orc_sumsq_f32.argtypes = [f32p, C.c_uint32]
         L.orc_sumsq_f32.restype = C.c_double
         L.orc_sumsq_f64.argtypes = [f64p, C.c_uint32]
@@ -72,6 +79,8 @@ def lib():
         L.orc_stream_get.restype = C.c_int
         L.orc_trace_get.argtypes = [C.c_void_p, C.c_uint32, f64p, C.c_uint64]
         L.orc_trace_get.restype = C.c_uint64
+        L.orc_extreme_threshold.argtypes = [C.c_uint32]
+        L.orc_extreme_threshold.restype = C.c_double
         _lib = L
     return _lib
 
@@ -122,6 +131,33 @@ def transform(x, k: int) -> np.ndarray:
     return y
 
 
+TRANSFORM_A4, TRANSFORM_ROTATION = 0, 1
+
+
+def decode_rotation(u1: int, u2: int, H: int):
+    a = np.zeros(2, np.uint32)
+    g = np.zeros(2, np.uint32)
+    cs = np.zeros(2, np.float64)
+    lib().orc_decode_rotation(u1, u2, H, a, g, cs)
+    return a, g, float(cs[0]), float(cs[1])
+
+
+def rotation_pass(P: np.ndarray, alpha, gamma, c: float, s: float) -> np.ndarray:
+    P = np.array(P, copy=True)
+    a = np.ascontiguousarray(alpha, np.uint32)
+    g = np.ascontiguousarray(gamma, np.uint32)
+    if P.dtype == np.float32:
+        lib().orc_rotation_pass_f32(P, P.size, a, g, c, s)
+    else:
+        P = P.astype(np.float64)
+        lib().orc_rotation_pass_f64(P, P.size, a, g, c, s)
+    return P
+
+
+def warmup_passes(n: int, transform: int = TRANSFORM_A4) -> int:
+    return int(lib().orc_warmup_passes(n, transform))
+
+
 def sumsq(P: np.ndarray) -> float:
     P = np.ascontiguousarray(P)
     if P.dtype == np.float32:
@@ -156,6 +192,17 @@ def cvt_f16(x) -> np.ndarray:
     return y
 
 
+def extreme_threshold(n: int) -> float:
+    return float(lib().orc_extreme_threshold(n))
+
+
+def extreme_counts(zmax_rows, c):
+    """(pools with an extreme, adjacent pairs with two) from per-pool maxima of
+    one stream, in pool order."""
+    e = np.asarray(zmax_rows) >= c
+    return int(e.sum()), int(np.count_nonzero(e[1:] & e[:-1]))
+
+
 def max_threads() -> int:
     return int(lib().orc_max_threads())
 
@@ -166,7 +213,8 @@ class Generator:
     """The oracle generator: same configuration surface as the GPU library."""
 
     def __init__(self, num_streams, pool_n=4096, R=2, pool_dtype="f32", chi2=CHI2_CUBIC,
-                 K=16, hazard=HAZ_NONE, warmup=0, trace=False):
+                 K=16, hazard=HAZ_NONE, warmup=0, trace=False, x_current=False, transform=0,
+                 mean=0.0, stddev=1.0):
         self.num_streams = int(num_streams)
         per_stream = None
         if np.ndim(pool_n) > 0:
@@ -177,7 +225,7 @@ class Generator:
             default = int(pool_n)
         self.pool_f64 = pool_dtype in ("f64", "float64", np.float64)
         cfg = _Config(self.num_streams, default, R, int(self.pool_f64), chi2, K, hazard, warmup,
-                      int(bool(trace)))
+                      int(bool(trace)), int(bool(x_current)), transform, 0, mean, stddev)
         self._pool_n = per_stream
         self._h = lib().orc_create(C.byref(cfg),
                                    per_stream.ctypes.data if per_stream is not None else None)
@@ -216,6 +264,7 @@ class Generator:
         return info, pool
 
     def trace(self, s: int, max_records: int = 1 << 20) -> np.ndarray:
-        buf = np.zeros(5 * max_records, np.float64)
+        """Per-pool records (Q, S, f, x, T, zmax), one row per pool produced."""
+        buf = np.zeros(6 * max_records, np.float64)
         c = lib().orc_trace_get(self._h, s, buf, max_records)
-        return buf[: 5 * c].reshape(c, 5)
+        return buf[: 6 * c].reshape(c, 6)

@@ -127,6 +127,57 @@ inline void quad_transform(const T x[4], int k, T y[4]) {
   y[3] = d - t;
 }
 
+// ---------------------------------------------------------------------------
+// Plane rotations (§5.3, the rann4 form): R(theta) = [[c, s], [-s, c]] with
+// c = (1 - t^2)/(1 + t^2), s = 2t/(1 + t^2), t held fixed for a whole pass;
+// theta itself is never computed.  R16: the pool is 2 rows of H = n/2; each
+// row is read through its own odd-multiplier affine map (rann4's pi1, pi2,
+// §5.4) from F0 (row 0) and F1 (row 1): gamma = F mod H,
+// alpha = 2((F >> 13) mod H/2) + 1 (bit fields disjoint for H <= 8192);
+// t = (F2 >> 8) 2^-24 in [0, 1); F3 bits 0 and 1 flip the signs of c and s
+// (so that the mean of every entry over passes vanishes, §5.2).  c and s are
+// computed in binary64 (t^2, 1 - t^2 and 1 + t^2 are exact) and rounded to
+// the pool type.  Pair q: a = row0[pi0(q)], b = row1[pi1(q)];
+// new row0[q] = c a + s b, new row1[q] = c b - s a (products and sums each
+// rounded in the pool type).
+// ---------------------------------------------------------------------------
+struct RotParams {
+  uint32_t alpha[2], gamma[2];
+  double c, s;
+};
+
+RotParams decode_rotation(uint64_t u1, uint64_t u2, uint32_t H) {
+  const uint32_t F[4] = {uint32_t(u1), uint32_t(u1 >> 32), uint32_t(u2), uint32_t(u2 >> 32)};
+  RotParams p;
+  for (int r = 0; r < 2; ++r) {
+    p.gamma[r] = F[r] & (H - 1);
+    p.alpha[r] = 2u * ((F[r] >> 13) & (H / 2 - 1)) + 1u;
+  }
+  const double t = double(F[2] >> 8) * 0x1p-24;
+  const double tt = t * t;
+  p.c = (1.0 - tt) / (1.0 + tt);
+  p.s = (2.0 * t) / (1.0 + tt);
+  if (F[3] & 1u) p.c = -p.c;
+  if (F[3] & 2u) p.s = -p.s;
+  return p;
+}
+
+template <class T>
+void run_rotation_pass(std::vector<T> &P, const RotParams &p, std::vector<T> &scratch) {
+  const uint32_t n = uint32_t(P.size());
+  const uint32_t H = n / 2;
+  const T c = T(p.c), s = T(p.s);
+  scratch.assign(n, T(0));
+  for (uint32_t q = 0; q < H; ++q) {
+    const T a = P[(p.alpha[0] * q + p.gamma[0]) & (H - 1)];
+    const T b = P[H + ((p.alpha[1] * q + p.gamma[1]) & (H - 1))];
+    const T ca = c * a, sb = s * b, cb = c * b, sa = s * a;
+    scratch[q] = ca + sb;
+    scratch[H + q] = cb - sa;
+  }
+  P.swap(scratch);
+}
+
 // Negative controls for the mixing requirement of §5.4 (several plausible
 // schemes fail).  Only the oracle has them; the tests use them to show that
 // the statistical checks can fail.
@@ -331,7 +382,25 @@ inline void store_out(void *out, uint64_t pos, T y, uint32_t dtype) {
 // ---------------------------------------------------------------------------
 struct PoolRecord {  // per produced pool, for the statistical tests
   double Q, S, f, x, Temit;
+  double zmax;  // largest |T(P[i] T(f))| over the n-1 emitted positions
 };
+
+// Extreme-value threshold for pools of n values (Section 5.7: a value large
+// enough to appear about once in ten pools).  q is the two-sided normal
+// quantile with P(|Z| > q) = erfc(q / sqrt 2) = 0.1 / n, found by bisection on
+// erfc (decreasing); c_n is q rounded up to a multiple of 2^-8.
+double extreme_threshold(uint32_t n) {
+  const double target = 0.1 / double(n);
+  double lo = 0.0, hi = 40.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (std::erfc(mid / std::sqrt(2.0)) > target)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return std::ceil(hi * 256.0) / 256.0;
+}
 
 template <class T>
 struct Stream {
@@ -356,12 +425,22 @@ struct Config {
   uint32_t hazard;  // Hazard (negative controls)
   uint32_t warmup;  // 0 = log2(n) + 4
   uint32_t trace;   // record PoolRecord per pool
+  uint32_t x_current;  // chi-square deviate from the current pool (fastnorm's choice)
+  uint32_t transform;  // 0: the 4x4 family; 1: plane rotations
+  double mean;         // added to every output when non-zero
+  double stddev;       // folded into the scale
 };
 
 inline uint32_t ilog2(uint32_t v) {
   uint32_t r = 0;
   while ((1u << r) < v) ++r;
   return r;
+}
+
+// Warm-up passes (R11): log2(n) + 4 for the 4x4 family; a rotation joins 2
+// values instead of 4, so its dependency sets grow half as fast: 2 log2(n) + 4.
+inline uint32_t warmup_passes(uint32_t n, uint32_t transform) {
+  return transform == 1 ? 2 * ilog2(n) + 4 : ilog2(n) + 4;
 }
 
 template <class T>
@@ -389,7 +468,7 @@ struct Gen {
       st.P[i] = T(c * 0x1p-22);
     }
     renormalise(st.P, sum_of_squares(st.P.data(), st.n));
-    const uint32_t W = cfg.warmup ? cfg.warmup : ilog2(st.n) + 4;
+    const uint32_t W = cfg.warmup ? cfg.warmup : warmup_passes(st.n, cfg.transform);
     for (uint32_t w = 0; w < W; ++w) one_pass(st);
     renormalise(st.P, sum_of_squares(st.P.data(), st.n));
     st.qlast = sum_of_squares(st.P.data(), st.n);
@@ -404,7 +483,10 @@ struct Gen {
   void one_pass(Stream<T> &st) {
     const uint64_t u1 = xorshift64_next(st.xs);
     const uint64_t u2 = xorshift64_next(st.xs);
-    run_pass(st.P, decode_pass(u1, u2, st.n / 4), cfg.hazard, st.scratch);
+    if (cfg.transform == 1)
+      run_rotation_pass(st.P, decode_rotation(u1, u2, st.n / 2), st.scratch);
+    else
+      run_pass(st.P, decode_pass(u1, u2, st.n / 4), cfg.hazard, st.scratch);
   }
 
   // Produce pool k (§5.5 and §5.7): R9 renormalise every K pools using the
@@ -420,7 +502,7 @@ struct Gen {
     const double Q = sum_of_squares(st.P.data(), st.n);
     const double last = double(st.P[st.n - 1]);
     double x = st.xnext;
-    if (cfg.hazard == kHazCurrentX) x = last;
+    if (cfg.hazard == kHazCurrentX || cfg.x_current) x = last;
     double S = 0.0, f = 1.0;
     if (cfg.chi2 != kChi2Off) {
       S = chi2_sample(cc, cfg.chi2, x);
@@ -429,25 +511,35 @@ struct Gen {
     st.f = f;
     st.xnext = f * last;
     st.qlast = Q;
-    if (cfg.trace) st.trace.push_back({Q, S, f, x, (f * f) * (Q - last * last)});
+    if (cfg.trace) {
+      // the standardised values the pool will emit: T(P[i] * T(f)), i < n-1
+      const T fT = T(f);
+      double zmax = 0.0;
+      for (uint32_t i = 0; i + 1 < st.n; ++i)
+        zmax = std::max(zmax, std::fabs(double(T(st.P[i] * fT))));
+      st.trace.push_back({Q, S, f, x, (f * f) * (Q - last * last), zmax});
+    }
     st.k += 1;
     st.cursor = 0;
   }
 
-  // R12: one emitted value is y_i = T(P[i] * T(f)) for i = 0..n-2, cast to
-  // the output type with round-to-nearest-even (a binary64 pool goes to the
-  // 16-bit types through binary32).  fill(c) continues the stream: values
-  // left in the current pool are emitted first.
+  // R12: one emitted value is y_i = T(P[i] * T(f * sigma)) for i = 0..n-2,
+  // plus T(mu) in the pool type when mu != 0 (Section 5.5: sigma and mu ride
+  // on the scale), cast to the output type with round-to-nearest-even (a
+  // binary64 pool goes to the 16-bit types through binary32).  fill(c)
+  // continues the stream: values left in the current pool are emitted first.
   void fill_stream(uint32_t s, uint64_t count, void *out, uint64_t off, uint32_t dtype) {
     Stream<T> &st = streams[s];
     if (!st.ready) init_stream(s);
     const Chi2Consts cc = chi2_consts(st.n);
+    const T muT = T(cfg.mean);
     while (count > 0) {
       if (st.cursor == st.n - 1) produce_pool(st, cc);
-      const T fT = T(st.f);
+      const T fT = T(st.f * cfg.stddev);
       const uint64_t take = std::min<uint64_t>(count, st.n - 1 - st.cursor);
       for (uint64_t j = 0; j < take; ++j) {
         T y = st.P[st.cursor + j] * fT;
+        if (cfg.mean != 0.0) y = y + muT;
         store_out(out, off + j, y, dtype);
       }
       st.cursor += uint32_t(take);
@@ -480,6 +572,11 @@ struct orc_config {
   uint32_t hazard;
   uint32_t warmup;
   uint32_t trace;
+  uint32_t x_current;
+  uint32_t transform;
+  uint32_t pad;
+  double mean;
+  double stddev;
 };
 
 struct orc_stream_info {
@@ -542,6 +639,44 @@ void orc_pass_f64(double *P, uint32_t n, int32_t k, const uint32_t *alpha, const
 
 void orc_transform_f64(const double *x, int32_t k, double *y) { quad_transform(x, k, y); }
 
+void orc_decode_rotation(uint64_t u1, uint64_t u2, uint32_t H, uint32_t *alpha, uint32_t *gamma,
+                         double *cs) {
+  const RotParams p = decode_rotation(u1, u2, H);
+  for (int r = 0; r < 2; ++r) {
+    alpha[r] = p.alpha[r];
+    gamma[r] = p.gamma[r];
+  }
+  cs[0] = p.c;
+  cs[1] = p.s;
+}
+
+static RotParams make_rot(const uint32_t *alpha, const uint32_t *gamma, double c, double s) {
+  RotParams p;
+  for (int r = 0; r < 2; ++r) {
+    p.alpha[r] = alpha[r];
+    p.gamma[r] = gamma[r];
+  }
+  p.c = c;
+  p.s = s;
+  return p;
+}
+
+void orc_rotation_pass_f32(float *P, uint32_t n, const uint32_t *alpha, const uint32_t *gamma,
+                           double c, double s) {
+  std::vector<float> v(P, P + n), t;
+  run_rotation_pass(v, make_rot(alpha, gamma, c, s), t);
+  std::copy(v.begin(), v.end(), P);
+}
+
+void orc_rotation_pass_f64(double *P, uint32_t n, const uint32_t *alpha, const uint32_t *gamma,
+                           double c, double s) {
+  std::vector<double> v(P, P + n), t;
+  run_rotation_pass(v, make_rot(alpha, gamma, c, s), t);
+  std::copy(v.begin(), v.end(), P);
+}
+
+uint32_t orc_warmup_passes(uint32_t n, uint32_t transform) { return warmup_passes(n, transform); }
+
 double orc_sumsq_f32(const float *P, uint32_t n) { return sum_of_squares(P, n); }
 double orc_sumsq_f64(const double *P, uint32_t n) { return sum_of_squares(P, n); }
 
@@ -568,7 +703,9 @@ void *orc_create(const orc_config *cfg, const uint32_t *pool_n) {
   if (!cfg || cfg->num_streams == 0 || cfg->R == 0) return nullptr;
   auto *g = new OrcGen();
   g->pool_f64 = cfg->pool_f64;
-  Config c{cfg->num_streams, cfg->R, cfg->chi2, cfg->K, cfg->hazard, cfg->warmup, cfg->trace};
+  if (!(cfg->stddev > 0.0) || cfg->transform > 1) return nullptr;
+  Config c{cfg->num_streams, cfg->R,         cfg->chi2,      cfg->K,    cfg->hazard, cfg->warmup,
+           cfg->trace,       cfg->x_current, cfg->transform, cfg->mean, cfg->stddev};
   std::vector<uint32_t> ns(cfg->num_streams);
   for (uint32_t s = 0; s < cfg->num_streams; ++s) {
     ns[s] = pool_n ? pool_n[s] : cfg->default_pool_n;
@@ -654,7 +791,9 @@ int orc_stream_get(void *h, uint32_t s, orc_stream_info *info, void *pool) {
   return g->pool_f64 ? fill_info(g->g64) : fill_info(g->g32);
 }
 
-// Per-pool records {Q, S, f, x, T} of stream s (tracing must be on).
+double orc_extreme_threshold(uint32_t n) { return extreme_threshold(n); }
+
+// Per-pool records {Q, S, f, x, T, zmax} of stream s (tracing must be on).
 uint64_t orc_trace_get(void *h, uint32_t s, double *buf, uint64_t max_records) {
   auto *g = static_cast<OrcGen *>(h);
   auto get = [&](auto &gen) -> uint64_t {
@@ -662,11 +801,12 @@ uint64_t orc_trace_get(void *h, uint32_t s, double *buf, uint64_t max_records) {
     const auto &tr = gen.streams[s].trace;
     const uint64_t c = std::min<uint64_t>(max_records, tr.size());
     for (uint64_t i = 0; i < c; ++i) {
-      buf[5 * i + 0] = tr[i].Q;
-      buf[5 * i + 1] = tr[i].S;
-      buf[5 * i + 2] = tr[i].f;
-      buf[5 * i + 3] = tr[i].x;
-      buf[5 * i + 4] = tr[i].Temit;
+      buf[6 * i + 0] = tr[i].Q;
+      buf[6 * i + 1] = tr[i].S;
+      buf[6 * i + 2] = tr[i].f;
+      buf[6 * i + 3] = tr[i].x;
+      buf[6 * i + 4] = tr[i].Temit;
+      buf[6 * i + 5] = tr[i].zmax;
     }
     return c;
   };

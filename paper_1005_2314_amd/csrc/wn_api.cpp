@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <string>
@@ -68,6 +69,17 @@ wn::Chi2Consts chi2_consts(uint32_t n) {
   return c;
 }
 
+// Extreme-value threshold of the fused statistics for pools of n values
+// (Section 5.7: a value expected about once in ten pools): the smallest
+// multiple of 2^-8 at which the two-sided normal tail erfc(c / sqrt 2) falls
+// to 0.1 / n or below.
+double extreme_threshold(uint32_t n) {
+  const double target = 0.1 / double(n);
+  uint32_t j = 0;
+  while (std::erfc(double(j) / (256.0 * std::sqrt(2.0))) > target) ++j;
+  return double(j) / 256.0;
+}
+
 // A pinned staging buffer and its device twin for one work list.  A slot is
 // reused only after the event recorded behind its last use has completed.
 struct ListSlot {
@@ -101,6 +113,8 @@ struct wn_gen {
   int device = 0;
   uint32_t num_streams = 0;
   uint32_t R = 1, K = 0, chi2 = 0;
+  uint32_t x_current = 0, transform = 0;
+  double mean = 0.0, stddev = 1.0;
   bool pool_f64 = false;
   std::vector<uint32_t> pool_n;     // per stream
   std::vector<uint64_t> pool_off;   // per stream, bytes
@@ -118,6 +132,7 @@ struct wn_gen {
   unsigned next_slot = 0;
   std::vector<uint8_t> seen;  // duplicate check scratch
   wn::Chi2Consts cc[wn::kNumSizes];  // per pool size 2^4 .. 2^14
+  double xthr[wn::kNumSizes];        // extreme-value thresholds, same sizes
   // launch choices (wn_tuning); defaults: LDS double buffer, graph replay
   uint32_t variant = 1;
   uint32_t wgs_per_cu = 0;
@@ -141,7 +156,15 @@ wn::KernelCommon common(const wn_gen *g, uint32_t n) {
   c.R = g->R;
   c.K = g->K;
   c.chi2 = g->chi2;
-  for (int i = 0; i < wn::kNumSizes; ++i) c.cc[i] = g->cc[i];
+  c.x_current = g->x_current;
+  c.has_mu = g->mean != 0.0;
+  c.transform = g->transform;
+  c.sigma = g->stddev;
+  c.mu = g->mean;
+  for (int i = 0; i < wn::kNumSizes; ++i) {
+    c.cc[i] = g->cc[i];
+    c.xthr[i] = g->xthr[i];
+  }
   return c;
 }
 
@@ -191,9 +214,41 @@ bool alloc_fault_injected() {
 
 }  // namespace
 
+namespace {
+struct StateBlobHeader {  // prefix of a saved state
+  uint64_t magic;         // "WNSTATE1"
+  uint32_t num_streams, pool_f64, R, K, chi2, x_current, transform, pad;
+  double mean, stddev;
+  uint64_t arena_bytes, hdr_bytes;
+};
+constexpr uint64_t kStateMagic = 0x3145544154534e57ull;  // "WNSTATE1" little-endian
+
+StateBlobHeader blob_header(const wn_gen *g) {
+  StateBlobHeader h{};
+  h.magic = kStateMagic;
+  h.num_streams = g->num_streams;
+  h.pool_f64 = g->pool_f64;
+  h.R = g->R;
+  h.K = g->K;
+  h.chi2 = g->chi2;
+  h.x_current = g->x_current;
+  h.transform = g->transform;
+  h.mean = g->mean;
+  h.stddev = g->stddev;
+  h.arena_bytes = g->arena_bytes;
+  h.hdr_bytes = sizeof(wn::StreamHdr) * g->num_streams;
+  return h;
+}
+}  // namespace
+
 extern "C" {
 
 uint32_t wn_version(void) { return 10000u; }
+
+double wn_extreme_threshold(uint32_t n) {
+  if (n < 16 || n > 16384 || !is_pow2(n)) return std::nan("");
+  return extreme_threshold(n);
+}
 
 const char *wn_last_error(void) { return g_last_error.c_str(); }
 
@@ -201,9 +256,19 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   if (!out_gen) return fail(WN_EINVAL, "wn_create: out_gen is NULL");
   *out_gen = nullptr;
   if (!cfg) return fail(WN_EINVAL, "wn_create: cfg is NULL");
-  if (cfg->struct_size != sizeof(wn_config))
-    return fail(WN_EINVAL, "wn_create: struct_size %u, expected %zu", cfg->struct_size,
-                sizeof(wn_config));
+  if (cfg->struct_size != sizeof(wn_config) && cfg->struct_size != WN_CONFIG_V1_SIZE)
+    return fail(WN_EINVAL, "wn_create: struct_size %u, expected %zu or %u", cfg->struct_size,
+                sizeof(wn_config), WN_CONFIG_V1_SIZE);
+  static_assert(offsetof(wn_config, chi2_source) == WN_CONFIG_V1_SIZE, "v1 prefix");
+  const bool v2 = cfg->struct_size == sizeof(wn_config);
+  const uint32_t x_src = v2 ? uint32_t(cfg->chi2_source) : 0u;
+  const uint32_t transform = v2 ? uint32_t(cfg->transform) : 0u;
+  const double mean = v2 ? cfg->mean : 0.0;
+  const double stddev = v2 ? cfg->stddev : 1.0;
+  if (x_src > 1) return fail(WN_EINVAL, "wn_create: unknown chi2_source %u", x_src);
+  if (transform > 1) return fail(WN_EINVAL, "wn_create: unknown transform %u", transform);
+  if (!(std::isfinite(mean)) || !(stddev > 0.0) || !std::isfinite(stddev))
+    return fail(WN_EINVAL, "wn_create: mean must be finite and stddev finite and positive");
   if (cfg->num_streams == 0) return fail(WN_EINVAL, "wn_create: num_streams must be >= 1");
   if (cfg->passes_per_output == 0 || cfg->passes_per_output > 64)
     return fail(WN_EINVAL, "wn_create: passes_per_output must be in [1, 64]");
@@ -236,6 +301,10 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   g->R = cfg->passes_per_output;
   g->K = cfg->renorm_period;
   g->chi2 = uint32_t(cfg->chi2);
+  g->x_current = x_src;
+  g->transform = transform;
+  g->mean = mean;
+  g->stddev = stddev;
   g->pool_f64 = cfg->pool_dtype == WN_F64;
   const size_t esz = g->pool_f64 ? 8 : 4;
   try {
@@ -319,7 +388,10 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
     release(g);
     return hip_fail(e, "wn_create: capture stream");
   }
-  for (int i = 0; i < wn::kNumSizes; ++i) g->cc[i] = chi2_consts(16u << i);
+  for (int i = 0; i < wn::kNumSizes; ++i) {
+    g->cc[i] = chi2_consts(16u << i);
+    g->xthr[i] = extreme_threshold(16u << i);
+  }
   *out_gen = g;
   return WN_OK;
 }
@@ -335,7 +407,9 @@ wn_status wn_seed(wn_gen *g, uint64_t seed, void *hip_stream) {
     a.c = common(g, g->sizes[i]);
     a.streams = g->d_seed_lists[i];
     a.nstreams = uint32_t(g->streams_of_size[i].size());
-    a.warmup = ilog2(g->sizes[i]) + 4;
+    // a rotation joins two values where the 4x4 transform joins four, so its
+    // dependency sets grow half as fast: twice the passes
+    a.warmup = (g->transform ? 2 : 1) * ilog2(g->sizes[i]) + 4;
     a.seed = seed;
     if ((e = wn::launch_seed(a, g->pool_f64, st)) != hipSuccess)
       return hip_fail(e, "wn_seed: launch");
@@ -849,6 +923,56 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
   cleanup();
   if ((e = record_last(g, st)) != hipSuccess) return hip_fail(e, "wn_autotune: event");
   if (best) *best = chosen;
+  return WN_OK;
+}
+
+size_t wn_state_size(const wn_gen *g) {
+  if (!g) return 0;
+  return sizeof(StateBlobHeader) + g->arena_bytes + sizeof(wn::StreamHdr) * g->num_streams;
+}
+
+wn_status wn_save_state(wn_gen *g, void *host_buf, size_t bytes) {
+  if (!g || !host_buf) return fail(WN_EINVAL, "wn_save_state: NULL argument");
+  if (bytes != wn_state_size(g))
+    return fail(WN_EINVAL, "wn_save_state: buffer of %zu bytes, need %zu", bytes,
+                wn_state_size(g));
+  if (!g->seeded) return fail(WN_ESTATE, "wn_save_state: generator not seeded");
+  hipError_t e = hipSetDevice(g->device);
+  if (e == hipSuccess && g->has_last) e = hipEventSynchronize(g->last);
+  if (e != hipSuccess) return hip_fail(e, "wn_save_state");
+  const StateBlobHeader h = blob_header(g);
+  auto *dst = static_cast<unsigned char *>(host_buf);
+  std::memcpy(dst, &h, sizeof(h));
+  if ((e = hipMemcpy(dst + sizeof(h), g->d_hdr, h.hdr_bytes, hipMemcpyDeviceToHost)) !=
+          hipSuccess ||
+      (e = hipMemcpy(dst + sizeof(h) + h.hdr_bytes, g->d_arena, h.arena_bytes,
+                     hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "wn_save_state: copy");
+  return WN_OK;
+}
+
+wn_status wn_load_state(wn_gen *g, const void *host_buf, size_t bytes) {
+  if (!g || !host_buf) return fail(WN_EINVAL, "wn_load_state: NULL argument");
+  if (bytes != wn_state_size(g))
+    return fail(WN_EINVAL, "wn_load_state: buffer of %zu bytes, need %zu", bytes,
+                wn_state_size(g));
+  StateBlobHeader h;
+  std::memcpy(&h, host_buf, sizeof(h));
+  const StateBlobHeader want = blob_header(g);
+  if (std::memcmp(&h, &want, sizeof(h)) != 0)
+    return fail(WN_EINVAL, "wn_load_state: the state was saved under another configuration");
+  hipError_t e = hipSetDevice(g->device);
+  if (e == hipSuccess && g->has_last) e = hipEventSynchronize(g->last);
+  if (e != hipSuccess) return hip_fail(e, "wn_load_state");
+  const auto *src = static_cast<const unsigned char *>(host_buf);
+  // pool offsets and sizes are the generator's own; the saved headers carry
+  // the same values (same configuration), so they can be copied as they are
+  if ((e = hipMemcpy(g->d_hdr, src + sizeof(h), h.hdr_bytes, hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(g->d_arena, src + sizeof(h) + h.hdr_bytes, h.arena_bytes,
+                     hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "wn_load_state: copy");
+  g->seeded = true;
   return WN_OK;
 }
 

@@ -69,10 +69,13 @@ __device__ __forceinline__ uint64_t stream_seed(uint64_t seed, uint64_t stream) 
 // gamma_m = F_m mod L and odd alpha_m = 2((F_m >> 12) mod L/2) + 1; the
 // transform index is the top two bits of F0.
 struct PassParams {
-  uint32_t k;
+  uint32_t k;  // 0..3: matrix A_{k+1}; kRotation: a plane-rotation pass
   uint32_t alpha[4];
   uint32_t gamma[4];
+  double c, s;  // rotation passes only
 };
+
+constexpr uint32_t kRotation = 4;
 
 __device__ __forceinline__ PassParams decode(uint64_t u1, uint64_t u2, uint32_t L) {
   const uint32_t F[4] = {uint32_t(u1), uint32_t(u1 >> 32), uint32_t(u2), uint32_t(u2 >> 32)};
@@ -83,7 +86,43 @@ __device__ __forceinline__ PassParams decode(uint64_t u1, uint64_t u2, uint32_t 
     p.alpha[m] = 2u * ((F[m] >> 12) & (L / 2 - 1)) + 1u;
   }
   p.k = F[0] >> 30;
+  p.c = p.s = 0.0;
   return p;
+}
+
+// Plane-rotation passes (Section 5.3, the rann4 form; Section 5.4 for the
+// maps).  The pool is two rows of H = n/2; row r is read through
+// q -> (alpha_r q + gamma_r) mod H with gamma_r = F_r mod H and odd
+// alpha_r = 2((F_r >> 13) mod H/2) + 1.  t = (F2 >> 8) 2^-24 in [0, 1) gives
+// c = (1 - t^2)/(1 + t^2) and s = 2t/(1 + t^2), computed in binary64 (t^2,
+// 1 - t^2, 1 + t^2 and 2t are exact, each quotient is rounded once); bits 0
+// and 1 of F3 negate c and s.  The angle itself is never formed.
+__device__ __forceinline__ PassParams decode_rotation(uint64_t u1, uint64_t u2, uint32_t H) {
+  const uint32_t F[4] = {uint32_t(u1), uint32_t(u1 >> 32), uint32_t(u2), uint32_t(u2 >> 32)};
+  PassParams p;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    p.gamma[r] = F[r] & (H - 1);
+    p.alpha[r] = 2u * ((F[r] >> 13) & (H / 2 - 1)) + 1u;
+  }
+  p.alpha[2] = p.alpha[3] = p.gamma[2] = p.gamma[3] = 0u;
+  p.k = kRotation;
+  const double t = __dmul_rn(double(F[2] >> 8), 0x1p-24);
+  const double tt = __dmul_rn(t, t);
+  const double den = __dadd_rn(1.0, tt);
+  double c = __ddiv_rn(__dsub_rn(1.0, tt), den);
+  double sn = __ddiv_rn(__dadd_rn(t, t), den);
+  if (F[3] & 1u) c = -c;
+  if (F[3] & 2u) sn = -sn;
+  p.c = c;
+  p.s = sn;
+  return p;
+}
+
+// the pass parameters of the configured transform for pool rows of length L = n/4
+__device__ __forceinline__ PassParams decode_for(uint32_t transform, uint64_t u1, uint64_t u2,
+                                                 uint32_t L) {
+  return transform ? decode_rotation(u1, u2, 2 * L) : decode(u1, u2, L);
 }
 
 // ---- the 4x4 transform (Section 5.3) -----------------------------------------
@@ -104,6 +143,18 @@ __device__ __forceinline__ void quad(T a, T b, T c, T d, T (&y)[4]) {
   y[1] = t - b;
   y[2] = a - t;
   y[3] = d - t;
+}
+
+// One rotation (c, s) of the pair (a, b): (c a + s b, c b - s a), every product
+// and sum rounded in the pool type (no fused multiply-add).
+__device__ __forceinline__ void rotate(float c, float s, float a, float b, float &y0, float &y1) {
+  y0 = __fadd_rn(__fmul_rn(c, a), __fmul_rn(s, b));
+  y1 = __fsub_rn(__fmul_rn(c, b), __fmul_rn(s, a));
+}
+__device__ __forceinline__ void rotate(double c, double s, double a, double b, double &y0,
+                                       double &y1) {
+  y0 = __dadd_rn(__dmul_rn(c, a), __dmul_rn(s, b));
+  y1 = __dsub_rn(__dmul_rn(c, b), __dmul_rn(s, a));
 }
 
 // ---- binary64 helpers ----------------------------------------------------------
@@ -221,7 +272,9 @@ __device__ __forceinline__ double widen(Half v) {
 }
 
 constexpr uint32_t kHistSlots = kHistBins + 2;  // bins, then below -8 and at or above 8
-constexpr size_t kStatsLds = 16 * sizeof(double) + ((kHistSlots * 4 + 15) / 16) * 16;
+// statistics LDS: 16 partial-sum slots, 4 per-wave flag words, the histogram
+constexpr size_t kStatsLds =
+    16 * sizeof(double) + 4 * sizeof(uint32_t) + ((kHistSlots * 4 + 15) / 16) * 16;
 static_assert(((kHistSlots * 4 + 15) / 16) * 16 - kHistSlots * 4 >= 8,
               "the histogram's padding holds the persistent kernel's item word");
 
@@ -363,10 +416,51 @@ struct Engine {
     for (int c = 0; c < NQ; ++c) quad<K>(x[c][0], x[c][1], x[c][2], x[c][3], y[c]);
   }
 
+  // Gather the pairs of a rotation pass from buffer RB and rotate them.  Pair
+  // q = h*L + c*BD + tid (h = 0, 1) reads row 0 at (alpha_0 q + gamma_0) mod H
+  // and row 1 at (alpha_1 q + gamma_1) mod H, H = 2L, and writes row 0 and row 1
+  // position q, which are elements h*L + c*BD + tid and (h+2)*L + c*BD + tid:
+  // the registers y[c][h] and y[c][h+2] of this thread.
+  template <int RB>
+  __device__ __forceinline__ void gather_rotate(const PassParams &p, bool renorm, double g) {
+    LdsT *P = lds_buf(RB);
+    const uint32_t L = len();
+    const uint32_t H = 2 * L;
+    constexpr uint32_t W = sizeof(T);
+    const uint32_t mask = (H - 1) * W;
+    using LdsB = __attribute__((address_space(3))) const unsigned char;
+    T x[NQ][4];  // x[c][h + 2r]: row r's operand of pair h*L + c*BD + tid
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const uint32_t a = p.alpha[r];
+      const uint32_t step = a * bd() * W;
+      LdsB *row = reinterpret_cast<LdsB *>(P + uint32_t(r) * H);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t first = __umul24(a * W, tid) + p.gamma[r] * W + a * (uint32_t(h) * L) * W;
+#pragma unroll
+        for (int c = 0; c < NQ; ++c)
+          x[c][h + 2 * r] = *reinterpret_cast<LdsT *>(row + ((first + step * uint32_t(c)) & mask));
+      }
+    }
+    if (renorm) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) x[c][m] = T(__dmul_rn(double(x[c][m]), g));
+    }
+    const T cT = T(p.c), sT = T(p.s);
+#pragma unroll
+    for (int c = 0; c < NQ; ++c)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) rotate(cT, sT, x[c][h], x[c][h + 2], y[c][h], y[c][h + 2]);
+  }
+
   template <int RB>
   __device__ __forceinline__ void pass_from(const PassParams &p, bool renorm, double g) {
     constexpr int WB = DB ? 1 - RB : RB;
     switch (p.k) {
+      case kRotation: gather_rotate<RB>(p, renorm, g); break;
       case 0: gather_transform<0, RB>(p, renorm, g); break;
       case 1: gather_transform<1, RB>(p, renorm, g); break;
       case 2: gather_transform<2, RB>(p, renorm, g); break;
@@ -429,6 +523,31 @@ struct Engine {
     return acc;
   }
 
+  // Largest |P[i]| over this thread's elements except the withheld n-1.
+  __device__ __forceinline__ T max_abs_emitted() const {
+    T mx = T(0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) {
+        const T v = y[c][m] < T(0) ? -y[c][m] : y[c][m];
+        if ((m < 3 || c < NQ - 1 || tid < bd() - 1) && v > mx) mx = v;
+      }
+    return mx;
+  }
+
+  // Block-wide OR of one predicate per thread through 4 LDS flag words (one
+  // per wave).  Ends with a barrier; two calls must be separated by a barrier.
+  __device__ __forceinline__ bool block_any(bool p, uint32_t *flags) const {
+    const bool w = __ballot(p) != 0ull;
+    if ((tid & 63) == 0) flags[tid >> 6] = w ? 1u : 0u;
+    __syncthreads();
+    const uint32_t nw = (bd() + 63) / 64;
+    uint32_t any = flags[0];
+    for (uint32_t i = 1; i < nw; ++i) any |= flags[i];
+    return any != 0u;
+  }
+
   template <bool NT, typename O>
   __device__ __forceinline__ static void put(O *p, O v) {
     if constexpr (!NT) {
@@ -442,9 +561,16 @@ struct Engine {
 
   // Emit pool positions [lo, hi) scaled by fT to out[obase + (i - lo)]; with
   // STATS, also accumulate each emitted value into `sa`.
+  // T(P[i] * fT), plus muT in the pool type when has_mu
+  __device__ __forceinline__ static T scaled(T v, T fT, bool has_mu, T muT) {
+    const T y = v * fT;
+    return has_mu ? T(y + muT) : y;
+  }
+
   template <bool NT, bool STATS, typename O>
   __device__ __forceinline__ void emit(O *__restrict__ out, uint64_t obase, uint32_t lo,
-                                       uint32_t hi, T fT, StatsAcc *sa) const {
+                                       uint32_t hi, T fT, StatsAcc *sa, bool has_mu = false,
+                                       T muT = T(0)) const {
     const uint32_t L = len();
     if (lo == 0 && hi == 4 * L - 1) {
       // a whole pool: every position but the withheld last one
@@ -453,7 +579,7 @@ struct Engine {
       for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int c = 0; c < NQ; ++c) {
-          const O v = Cast<O>::from(T(y[c][m] * fT));
+          const O v = Cast<O>::from(scaled(y[c][m], fT, has_mu, muT));
           if (m < 3 || c < NQ - 1 || tid < bd() - 1) {
             put<NT>(dst + (uint32_t(m) * L + uint32_t(c) * bd()), v);
             if constexpr (STATS) sa->add(widen(v));
@@ -467,7 +593,7 @@ struct Engine {
       for (int c = 0; c < NQ; ++c) {
         const uint32_t i = pos(m, c);
         if (i >= lo && i < hi) {
-          const O v = Cast<O>::from(T(y[c][m] * fT));
+          const O v = Cast<O>::from(scaled(y[c][m], fT, has_mu, muT));
           put<NT>(out + (obase + (i - lo)), v);
           if constexpr (STATS) sa->add(widen(v));
         }
@@ -517,9 +643,13 @@ __device__ __forceinline__ uint64_t *misc_word(unsigned char *smem, size_t pool_
   return reinterpret_cast<uint64_t *>(smem + pool_bytes + 4 * sizeof(double)) + w;
 }
 
-__device__ __forceinline__ uint32_t *stats_hist(unsigned char *smem, size_t pool_bytes) {
+__device__ __forceinline__ uint32_t *stats_flags(unsigned char *smem, size_t pool_bytes) {
   return reinterpret_cast<uint32_t *>(smem + pool_bytes + 4 * sizeof(double) + kMiscLds +
                                       16 * sizeof(double));
+}
+
+__device__ __forceinline__ uint32_t *stats_hist(unsigned char *smem, size_t pool_bytes) {
+  return stats_flags(smem, pool_bytes) + 4;
 }
 
 __device__ __forceinline__ void hist_clear(uint32_t *hist) {
@@ -574,7 +704,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
   for (uint32_t w = 0; w < a.warmup; ++w) {
     const uint64_t u1 = xs_next(xs);
     const uint64_t u2 = xs_next(xs);
-    e.pass(decode(u1, u2, e.len()), false, 1.0);
+    e.pass(decode_for(a.c.transform, u1, u2, e.len()), false, 1.0);
     __syncthreads();
   }
   Q = e.sumsq();
@@ -615,12 +745,16 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   auto e = make_engine<T, NQ, SMALL, DB>(smem, n);
   StatsAcc sa;
   double t_sum = 0.0, t_sumsq = 0.0, t_lag = 0.0, tprev = 0.0;
-  uint64_t pools = 0, t_pairs = 0;
+  uint64_t pools = 0, t_pairs = 0, x_pools = 0, x_pairs = 0;
+  uint32_t xprev = 0;
+  uint32_t *xflags = nullptr;
   const uint64_t emitted = count;
   if constexpr (STATS) {
     sa.hist = stats_hist(smem, size_t(n) * sizeof(T) * (DB ? 2 : 1));
+    xflags = stats_flags(smem, size_t(n) * sizeof(T) * (DB ? 2 : 1));
     hist_clear(sa.hist);  // published by the barrier after the pool load
     tprev = h->tprev;
+    xprev = h->xprev;
   }
   const Chi2Consts &cc = a.c.cc[__builtin_ctz(n) - 4];
   uint64_t xs = h->xs;
@@ -635,9 +769,12 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   e.load_global(gpool);
   __syncthreads();
 
+  const bool has_mu = a.c.has_mu != 0;
+  const T muT = T(a.c.mu);
   if (cursor < n - 1) {
     const uint32_t take = take_of(count, n - 1 - cursor);
-    e.template emit<NT, STATS>(out, obase, cursor, cursor + take, T(f), &sa);
+    e.template emit<NT, STATS>(out, obase, cursor, cursor + take, T(__dmul_rn(f, a.c.sigma)), &sa,
+                               has_mu, muT);
     obase += take;
     count -= take;
     cursor += take;
@@ -650,13 +787,14 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     for (uint32_t r = 0; r < a.c.R; ++r) {
       const uint64_t u1 = xs_next(xs);
       const uint64_t u2 = xs_next(xs);
-      e.pass(decode(u1, u2, e.len()), renorm && r == 0, g);
+      e.pass(decode_for(a.c.transform, u1, u2, e.len()), renorm && r == 0, g);
       if (r + 1 < a.c.R) __syncthreads();
     }
     const double Q = e.sumsq();
     const double last = double(e.last());
     double fk = 1.0;
-    if (a.c.chi2 != kChi2Off) fk = __dsqrt_rn(__ddiv_rn(chi2_sample(cc, a.c.chi2, xnext), Q));
+    if (a.c.chi2 != kChi2Off)
+      fk = __dsqrt_rn(__ddiv_rn(chi2_sample(cc, a.c.chi2, a.c.x_current ? last : xnext), Q));
     if (e.tid == 0) flag_fault(a.c.err, Q);
     f = fk;
     xnext = __dmul_rn(fk, last);
@@ -674,10 +812,17 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
       }
       tprev = Tk;
       pools += 1;
+      // Section 5.7: does the pool emit a value with |T(P[i] T(f))| >= c_n?
+      // Rounding is monotone, so the largest such value is T(max|P[i]| T(f)).
+      const T zmax = T(e.max_abs_emitted() * T(fk));
+      const uint32_t ek = e.block_any(double(zmax) >= a.c.xthr[__builtin_ctz(n) - 4], xflags);
+      x_pools += ek;
+      if (k > 0) x_pairs += ek & xprev;
+      xprev = ek;
     }
     k += 1;
     const uint32_t take = take_of(count, n - 1);
-    e.template emit<NT, STATS>(out, obase, 0, take, T(f), &sa);
+    e.template emit<NT, STATS>(out, obase, 0, take, T(__dmul_rn(f, a.c.sigma)), &sa, has_mu, muT);
     obase += take;
     count -= take;
     cursor = take;
@@ -691,7 +836,10 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     h->xnext = xnext;
     h->qlast = qlast;
     h->cursor = cursor;
-    if constexpr (STATS) h->tprev = tprev;
+    if constexpr (STATS) {
+      h->tprev = tprev;
+      h->xprev = xprev;
+    }
   }
   if constexpr (STATS) {
     // the request's moments: a pairwise tree over the threads, one slot set per
@@ -713,6 +861,8 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
       pp.count = emitted;
       pp.pools = pools;
       pp.t_pairs = t_pairs;
+      pp.x_pools = x_pools;
+      pp.x_pairs = x_pairs;
     }
     hist_flush(sa.hist, a.stats);
     __syncthreads();  // slots and histogram are reused by the next item

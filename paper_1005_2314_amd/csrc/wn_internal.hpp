@@ -3,12 +3,15 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace wn {
 
-// Per-stream header in device memory, 64 bytes.  The pool itself lives in the
-// state arena at byte offset pool_off, in natural element order.
+// Per-stream header in device memory, two 64-byte lines: generation reads and
+// writes only the first; the second carries statistics state between calls.
+// The pool itself lives in the state arena at byte offset pool_off, in natural
+// element order.
 struct StreamHdr {
   uint64_t xs;        // xorshift64 state
   uint64_t k;         // pools produced since seeding
@@ -19,8 +22,12 @@ struct StreamHdr {
   uint32_t n;         // pool size
   uint32_t cursor;    // next pool position to emit; n-1 = used up
   double tprev;       // centred emitted sum of squares of the current pool (statistics)
+  // second line (statistics only)
+  uint32_t xprev;     // 1 if the current pool holds an extreme value (statistics)
+  uint32_t pad_[15];
 };
-static_assert(sizeof(StreamHdr) == 64, "header must stay 64 bytes");
+static_assert(sizeof(StreamHdr) == 128, "header is two 64-byte lines");
+static_assert(offsetof(StreamHdr, xprev) == 64, "generation state stays in the first line");
 
 // Chi-square constants for one pool size (computed on the host).
 struct Chi2Consts {
@@ -40,8 +47,9 @@ struct StatsPartial {
   double moment[4];  // sums of y, y^2, y^3, y^4
   double t_sum, t_sumsq, t_lag;
   uint64_t count, pools, t_pairs;
+  uint64_t x_pools, x_pairs;  // pools with an extreme value; successive pairs of them
 };
-static_assert(sizeof(StatsPartial) == 80, "partial layout");
+static_assert(sizeof(StatsPartial) == 96, "partial layout");
 
 constexpr uint32_t kHistBins = 4096;  // floor(256 y) + 2048 for y in [-8, 8)
 
@@ -55,6 +63,7 @@ struct StatsOut {
   uint64_t t_pairs;
   double t_lag;
   uint64_t hist[kHistBins];
+  uint64_t x_pools, x_pairs;
 };
 
 enum : uint32_t { kChi2Cubic = 0, kChi2Off = 1, kChi2Fisher = 2, kChi2WH = 3 };
@@ -70,7 +79,14 @@ struct KernelCommon {
   uint32_t R;     // passes per emitted pool
   uint32_t K;     // renormalisation period (0 = never)
   uint32_t chi2;  // chi-square mode
+  uint32_t x_current;  // chi-square deviate from the current pool's last value (control)
+  uint32_t has_mu;     // add mu to every output
+  uint32_t transform;  // 0: the 4x4 family A1 D_k; 1: plane rotations
+  uint32_t pad_;
+  double sigma;        // folded into the scale: T(f * sigma)
+  double mu;
   Chi2Consts cc[kNumSizes];  // per pool size, index log2(n) - 4
+  double xthr[kNumSizes];    // extreme-value threshold per pool size (statistics)
 };
 
 struct SeedArgs {

@@ -20,11 +20,11 @@ __global__ __launch_bounds__(kBlock) void k_stats_zero(uint64_t *words, uint32_t
 __global__ __launch_bounds__(kBlock) void k_stats_reduce(const StatsPartial *p, uint32_t nreq,
                                                          StatsOut *out) {
   __shared__ double slots[7][4];
-  __shared__ unsigned long long icount[3];
+  __shared__ unsigned long long icount[5];
   const uint32_t t = threadIdx.x;
-  if (t < 3) icount[t] = 0ull;
+  if (t < 5) icount[t] = 0ull;
   double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  unsigned long long c0 = 0, c1 = 0, c2 = 0;
+  unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0;
   for (uint32_t j = t; j < nreq; j += kBlock) {
     const StatsPartial &q = p[j];
     acc[0] = __dadd_rn(acc[0], q.moment[0]);
@@ -37,11 +37,15 @@ __global__ __launch_bounds__(kBlock) void k_stats_reduce(const StatsPartial *p, 
     c0 += q.count;
     c1 += q.pools;
     c2 += q.t_pairs;
+    c3 += q.x_pools;
+    c4 += q.x_pairs;
   }
   __syncthreads();
   atomicAdd(&icount[0], c0);
   atomicAdd(&icount[1], c1);
   atomicAdd(&icount[2], c2);
+  atomicAdd(&icount[3], c3);
+  atomicAdd(&icount[4], c4);
 #pragma unroll
   for (int f = 0; f < 7; ++f) {
     const double w = wave_pairwise_sum(acc[f]);
@@ -63,6 +67,8 @@ __global__ __launch_bounds__(kBlock) void k_stats_reduce(const StatsPartial *p, 
     out->count = icount[0];
     out->pools = icount[1];
     out->t_pairs = icount[2];
+    out->x_pools = icount[3];
+    out->x_pairs = icount[4];
   }
 }
 

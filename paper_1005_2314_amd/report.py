@@ -158,6 +158,10 @@ def quality(W, inputs, stream):
     tv = sum(s.t_sumsq for s in sts) / P - tm * tm
     pairs = sum(s.t_pairs for s in sts)
     corr = (sum(s.t_lag for s in sts) / pairs - tm * tm) / tv
+    xpools = sum(s.x_pools for s in sts)
+    xpairs = sum(s.x_pairs for s in sts)
+    xrate = xpools / P
+    xexp = pairs * xrate * xrate
     g.close()
     return {"normals": N, "ms_with_stats": ms, "normals_per_s_with_stats": N / ms * 1e3,
             "ms_per_chunk_without_stats": t_plain,
@@ -167,6 +171,9 @@ def quality(W, inputs, stream):
             "hist_chi2": chi2, "hist_dof": int(np.count_nonzero(keep)) - 1,
             "pool_sum_mean_minus_nu": tm, "pool_sum_var_over_2nu": tv / (2 * (w["pool_n"] - 1)),
             "successive_pool_corr": corr, "pool_pairs": pairs,
+            "extreme_threshold": W.extreme_threshold(w["pool_n"]), "extreme_pool_rate": xrate,
+            "extreme_adjacent_pairs": xpairs, "extreme_adjacent_expected": xexp,
+            "extreme_adjacent_z": (xpairs - xexp) / math.sqrt(xexp),
             "below": sum(s.below for s in sts), "above": sum(s.above for s in sts)}
 
 

@@ -20,16 +20,24 @@ STATUS_NAMES = {0: "WN_OK", 1: "WN_EINVAL", 2: "WN_ENOMEM", 3: "WN_EDEVICE", 4: 
 
 # every symbol include/wn.h and include/wn_bench.h declare
 EXPORTED = ("wn_create", "wn_seed", "wn_fill", "wn_sync", "wn_get_stream", "wn_destroy",
+            "wn_state_size", "wn_save_state", "wn_load_state",
             "wn_last_error", "wn_version", "wn_set_tuning", "wn_get_tuning", "wn_autotune",
-            "wn_fill_stats", "wn_bench_store", "wn_bench_traffic",
+            "wn_fill_stats", "wn_extreme_threshold", "wn_bench_store", "wn_bench_traffic",
             "wn_bench_box_muller")
+
+
+WN_X_PREVIOUS, WN_X_CURRENT = 0, 1
+WN_TRANSFORM_A4, WN_TRANSFORM_ROTATION = 0, 1
+WN_CONFIG_V1_SIZE = 40
 
 
 class wn_config(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("num_streams", C.c_uint32),
                 ("pool_n", C.POINTER(C.c_uint32)), ("default_pool_n", C.c_uint32),
                 ("passes_per_output", C.c_uint32), ("pool_dtype", C.c_int),
-                ("chi2", C.c_int), ("renorm_period", C.c_uint32), ("device", C.c_int)]
+                ("chi2", C.c_int), ("renorm_period", C.c_uint32), ("device", C.c_int),
+                ("chi2_source", C.c_int), ("transform", C.c_int), ("mean", C.c_double),
+                ("stddev", C.c_double)]
 
 
 class wn_stream_info(C.Structure):
@@ -51,7 +59,8 @@ class wn_stats(C.Structure):
     _fields_ = [("count", C.c_uint64), ("moment", C.c_double * 4), ("below", C.c_uint64),
                 ("above", C.c_uint64), ("pools", C.c_uint64), ("t_sum", C.c_double),
                 ("t_sumsq", C.c_double), ("t_pairs", C.c_uint64), ("t_lag", C.c_double),
-                ("hist", C.c_uint64 * HIST_BINS)]
+                ("hist", C.c_uint64 * HIST_BINS), ("x_pools", C.c_uint64),
+                ("x_pairs", C.c_uint64)]
 
 
 class WnError(RuntimeError):
@@ -69,6 +78,12 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        # PyTorch ships its own HIP runtime under the same soname as the system
+        # one (libamdhip64.so.7); whichever is loaded first serves the whole
+        # process.  Load torch's first, so that the library runs on the runtime
+        # that owns the tensors and streams it is given (the other order leaves
+        # torch without a device).
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.wn_create.argtypes = [C.POINTER(wn_config), C.POINTER(vp)]
@@ -98,6 +113,14 @@ def load():
         L.wn_fill_stats.argtypes = [vp, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
                                     vp, C.c_int, vp, vp]
         L.wn_fill_stats.restype = C.c_int
+        L.wn_extreme_threshold.argtypes = [C.c_uint32]
+        L.wn_extreme_threshold.restype = C.c_double
+        L.wn_state_size.argtypes = [vp]
+        L.wn_state_size.restype = C.c_size_t
+        L.wn_save_state.argtypes = [vp, vp, C.c_size_t]
+        L.wn_save_state.restype = C.c_int
+        L.wn_load_state.argtypes = [vp, vp, C.c_size_t]
+        L.wn_load_state.restype = C.c_int
         L.wn_bench_store.argtypes = [vp, C.c_uint64, C.c_uint32, vp]
         L.wn_bench_store.restype = C.c_int
         L.wn_bench_traffic.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.c_uint64, vp]
@@ -164,7 +187,8 @@ def wn_bench_box_muller(out_ptr, count, out_dtype, seed, fast=False, stream=None
 
 
 def make_config(num_streams, pool_n=4096, R=2, pool_dtype=WN_F32, chi2=WN_CHI2_CUBIC, K=16,
-                device=0):
+                device=0, chi2_source=WN_X_PREVIOUS, transform=WN_TRANSFORM_A4, mean=0.0,
+                stddev=1.0):
     cfg = wn_config()
     cfg.struct_size = C.sizeof(wn_config)
     cfg.num_streams = int(num_streams)
@@ -181,10 +205,19 @@ def make_config(num_streams, pool_n=4096, R=2, pool_dtype=WN_F32, chi2=WN_CHI2_C
     cfg.chi2 = int(chi2)
     cfg.renorm_period = int(K)
     cfg.device = int(device)
+    cfg.chi2_source = int(chi2_source)
+    cfg.transform = int(transform)
+    cfg.mean = float(mean)
+    cfg.stddev = float(stddev)
     return cfg, keep
 
 
 _TORCH_DTYPES = None
+
+
+def extreme_threshold(n):
+    """c_n of the extreme-pool statistics (wn_extreme_threshold); NaN for a bad n."""
+    return float(load().wn_extreme_threshold(int(n)))
 
 
 def torch_dtype(out_dtype):
@@ -197,8 +230,10 @@ class Generator:
     """A set of independent streams on one GPU (owns a ``wn_gen``)."""
 
     def __init__(self, num_streams, pool_n=4096, R=2, pool_dtype=WN_F32, chi2=WN_CHI2_CUBIC,
-                 K=16, device=0):
-        self.cfg, keep = make_config(num_streams, pool_n, R, pool_dtype, chi2, K, device)
+                 K=16, device=0, chi2_source=WN_X_PREVIOUS, transform=WN_TRANSFORM_A4,
+                 mean=0.0, stddev=1.0):
+        self.cfg, keep = make_config(num_streams, pool_n, R, pool_dtype, chi2, K, device,
+                                     chi2_source, transform, mean, stddev)
         self.num_streams = int(num_streams)
         self.pool_f64 = pool_dtype == WN_F64
         self.device = device
@@ -313,6 +348,16 @@ class Generator:
                                  C.c_void_p(out.data_ptr()), dt, self._stream_handle(stream),
                                  C.byref(t)))
         return t
+
+    def save_state(self) -> bytes:
+        """Checkpoint of every stream (host bytes)."""
+        n = load().wn_state_size(self._h)
+        buf = C.create_string_buffer(n)
+        check(load().wn_save_state(self._h, buf, n))
+        return buf.raw
+
+    def load_state(self, blob: bytes):
+        check(load().wn_load_state(self._h, C.c_char_p(blob), len(blob)))
 
     def stream_state(self, s: int):
         info = wn_stream_info()

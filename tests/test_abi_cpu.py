@@ -32,9 +32,31 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_config_struct_layout():
-    # pointer member forces 8-byte alignment: 4+4+8+4*5+4 = 40
-    assert C.sizeof(W.wn_config) == 40
+    # version 1 prefix (pointer member forces 8-byte alignment): 4+4+8+4*5+4 = 40;
+    # version 2 adds two enums and two doubles
+    assert W.wn_config.chi2_source.offset == W.WN_CONFIG_V1_SIZE == 40
+    assert C.sizeof(W.wn_config) == 64
     assert C.sizeof(W.wn_stream_info) == 48
+    assert C.sizeof(W.wn_stats) == 8 * (1 + 4 + 2 + 1 + 2 + 1 + 1) + 8 * W.HIST_BINS + 16
+    assert W.wn_stats.x_pools.offset == W.wn_stats.hist.offset + 8 * W.HIST_BINS
+
+
+def test_version1_config_accepted_and_v2_fields_validated():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("checks the validation that precedes device selection")
+    cfg, _ = W.make_config(2, 1024)
+    cfg.struct_size = W.WN_CONFIG_V1_SIZE
+    with pytest.raises(W.WnError) as ei:  # valid v1 struct: fails only for want of a device
+        W.wn_create(cfg)
+    assert ei.value.status == W.WN_EDEVICE
+    for field, value in (("stddev", 0.0), ("stddev", float("inf")), ("mean", float("nan")),
+                         ("chi2_source", 2), ("transform", 9)):
+        cfg, _ = W.make_config(2, 1024)
+        setattr(cfg, field, value)
+        with pytest.raises(W.WnError) as ei:
+            W.wn_create(cfg)
+        assert ei.value.status == W.WN_EINVAL, field
 
 
 @pytest.mark.parametrize("kw", [
@@ -76,3 +98,18 @@ def test_no_device_is_edevice():
     with pytest.raises(W.WnError) as ei:
         W.wn_create(cfg)
     assert ei.value.status == W.WN_EDEVICE
+
+
+def test_extreme_threshold_is_the_normal_quantile_on_the_grid():
+    # host-only entry point: the two-sided normal quantile for a rate of 0.1/n
+    # per value, rounded up to a multiple of 2^-8 (checked against scipy)
+    import math
+    from scipy import special
+    for e in range(4, 15):
+        n = 1 << e
+        q = math.sqrt(2.0) * special.erfcinv(0.1 / n)
+        frac = q * 256 - math.floor(q * 256)
+        assert 1e-9 < frac < 1 - 1e-9  # not on the grid: the rounding is unambiguous
+        assert W.extreme_threshold(n) == math.ceil(q * 256) / 256
+    for bad in (0, 8, 100, 32768):
+        assert math.isnan(W.extreme_threshold(bad))

@@ -1,0 +1,106 @@
+"""GPU checks of the configuration extensions: location/scale (mu, sigma) on
+the scale factor, fastnorm's current-pool chi-square source, version-1
+configurations, and checkpoints that reproduce a stream bit for bit."""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import Pair, assert_bits_equal, bits, to_numpy_bits
+from oracle import oracle as O
+from paper_1005_2314_amd import wn as W
+
+pytestmark = pytest.mark.gpu
+
+
+class ExtPair(Pair):
+    def __init__(self, ns, n, R, pool="f32", seed=1, **ext):
+        pool_dtype = W.WN_F64 if pool == "f64" else W.WN_F32
+        self.gpu = W.Generator(ns, pool_n=n, R=R, pool_dtype=pool_dtype,
+                               chi2_source=int(ext.get("x_current", False)),
+                               mean=ext.get("mean", 0.0), stddev=ext.get("stddev", 1.0))
+        self.orc = O.Generator(ns, pool_n=n, R=R, pool_dtype=pool, **ext)
+        self.gpu.seed(seed)
+        self.orc.seed(seed)
+
+
+@pytest.mark.parametrize("pool,out", [("f32", W.WN_F32), ("f32", W.WN_BF16), ("f64", W.WN_F64),
+                                      ("f64", W.WN_F16)])
+@pytest.mark.parametrize("mean,stddev", [(0.0, 3.0), (-2.5, 0.125), (1e-3, 1.0)])
+def test_mean_stddev_bit_exact(pool, out, mean, stddev):
+    p = ExtPair(4, 1024, 2, pool=pool, mean=mean, stddev=stddev)
+    g, o = p.fill(np.arange(4), [3 * 1023 + 5] * 4, out)
+    assert_bits_equal(g, o, "affine")
+    g, o = p.fill([2, 0], [1500, 77], out)
+    assert_bits_equal(g, o, "work list")
+
+
+def test_current_pool_source_bit_exact():
+    p = ExtPair(3, 4096, 2, x_current=True)
+    g, o = p.fill(np.arange(3), [20000] * 3)
+    assert_bits_equal(g, o, "current-pool source")
+
+
+def test_version1_config_struct():
+    cfg, _ = W.make_config(2, 1024, R=2)
+    cfg.struct_size = W.WN_CONFIG_V1_SIZE
+    cfg.mean = 5.0  # ignored for a version-1 struct
+    h = W.wn_create(cfg)
+    try:
+        W.wn_seed(h, 1, None)
+        import torch
+        out = torch.empty(3000, device="cuda")
+        W.wn_fill(h, [0, 1], [1500, 1500], W.C.c_void_p(out.data_ptr()), W.WN_F32, None)
+        torch.cuda.synchronize()
+        o = O.Generator(2, pool_n=1024, R=2)
+        o.seed(1)
+        assert_bits_equal(to_numpy_bits(out), bits(o.fill([0, 1], [1500, 1500])), "v1")
+    finally:
+        W.wn_destroy(h)
+
+
+def test_checkpoint_reproduces_outputs():
+    sizes = np.array([1024, 4096, 2048, 1024], np.uint32)
+    p = Pair(4, pool_n=sizes, R=2, seed=9)
+    p.fill([0, 1, 2, 3], [5000, 3000, 1, 7000])
+    blob = p.gpu.save_state()
+    first = p.gpu.fill([3, 1, 0], [10000, 2, 4093])
+    import torch
+    torch.cuda.synchronize()
+    first = to_numpy_bits(first)
+    p.gpu.load_state(blob)
+    again = to_numpy_bits(p.gpu.fill([3, 1, 0], [10000, 2, 4093]))
+    np.testing.assert_array_equal(first, again)
+    o = bits(p.orc.fill([3, 1, 0], [10000, 2, 4093]))
+    assert_bits_equal(again, o, "after restore")
+    # a state from another configuration is refused
+    other = W.Generator(4, pool_n=sizes, R=3)
+    with pytest.raises(W.WnError) as ei:
+        other.load_state(blob)
+    assert ei.value.status == W.WN_EINVAL
+
+
+def test_save_before_seed_is_estate():
+    g = W.Generator(2, pool_n=64, R=1)
+    with pytest.raises(W.WnError) as ei:
+        g.save_state()
+    assert ei.value.status == W.WN_ESTATE
+
+
+def test_library_first_then_torch_in_a_fresh_process():
+    # the binding loads torch's HIP runtime before the library, so a program
+    # that creates a generator before it touches torch still gets a device
+    import subprocess
+    import sys
+    code = ("from paper_1005_2314_amd import wn as W\n"
+            "g = W.Generator(2, pool_n=1024, R=2)\n"
+            "g.seed(1)\n"
+            "y = g.fill([1], [3000])\n"
+            "import torch\n"
+            "torch.cuda.synchronize()\n"
+            "print('ok', y.numel(), bool(torch.isfinite(y).all()))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "ok 3000 True" in r.stdout

@@ -18,6 +18,13 @@ from paper_1005_2314_amd import wn as W
 pytestmark = pytest.mark.gpu
 
 
+def extreme_expected(tr, first, n):
+    """(x_pools, x_pairs) over the pools tr[first:] of one stream's trace."""
+    e = tr[:, 5] >= O.extreme_threshold(n)
+    xp = sum(int(e[k] and e[k - 1]) for k in range(max(first, 1), len(e)))
+    return int(e[first:].sum()), xp
+
+
 def expected(y, trace_rows, pairs, n):
     y = y.astype(np.float64)
     y2 = y * y
@@ -83,8 +90,12 @@ def test_stats_match_oracle(n, pool, dtype):
         else:
             y = o
         rows, pairs = [], []
+        xp_exp = [0, 0]
         for s in streams:
             tr = orc.trace(int(s))
+            a, b = extreme_expected(tr, prev_pools[int(s)], n)
+            xp_exp[0] += a
+            xp_exp[1] += b
             new = tr[prev_pools[int(s)]:]
             for i in range(len(new)):
                 k = prev_pools[int(s)] + i
@@ -92,8 +103,9 @@ def test_stats_match_oracle(n, pool, dtype):
                     pairs.append((tr[k, 4] - (n - 1)) * (tr[k - 1, 4] - (n - 1)))
             rows.extend(new)
             prev_pools[int(s)] = len(tr)
-        ex = expected(y, np.array(rows).reshape(-1, 5), np.array(pairs), n)
+        ex = expected(y, np.array(rows).reshape(-1, 6), np.array(pairs), n)
         check(st, ex, max(len(y), 1))
+        assert (st.x_pools, st.x_pairs) == tuple(xp_exp), call
 
 
 def test_stats_do_not_depend_on_launch_form():
@@ -151,3 +163,27 @@ def test_throughput_quality_chunk_statistics():
     # successive pools of a stream: correlation of their sums far below detection
     corr = (st.t_lag / st.t_pairs - tm * tm) / tv
     assert abs(corr) < 5 / math.sqrt(st.t_pairs)
+
+
+def test_extreme_pools_cluster_at_full_size():
+    """Section 5.7 on the GPU: with one pass per pool (n = 64) rare values
+    cluster in adjacent pools; three passes per emitted pool weaken it."""
+    import torch
+    n, ns, per = 64, 4096, 2000 * 63
+    ratios = []
+    for R in (1, 3):
+        g = W.Generator(ns, pool_n=n, R=R)
+        g.seed(12)
+        out = torch.empty(ns * per, device="cuda")
+        buf = g.stats_buffer()
+        g.fill_stats_into(out, np.arange(ns), [per] * ns, buf)
+        torch.cuda.synchronize()
+        st = g.read_stats(buf)
+        p = st.x_pools / st.pools
+        assert 0.07 < p < 0.11
+        expected = st.t_pairs * p * p
+        ratios.append(st.x_pairs / expected)
+        if R == 1:
+            assert (st.x_pairs - expected) / math.sqrt(expected) > 10
+        del out
+    assert ratios[1] - 1 < 0.5 * (ratios[0] - 1)

@@ -273,3 +273,43 @@ def test_renormalisation_holds_the_norm():
     g.fill([0], [3000 * (n - 1)])
     Q = g.trace(0)[:, 0]
     assert np.max(np.abs(Q / n - 1)) < 1e-5
+
+
+# ---- location/scale and the chi-square deviate source ---------------------------
+
+def test_power_of_two_sigma_scales_outputs_exactly():
+    """T(f * 2) = 2 T(f) and P * 2fT = 2 (P * fT) exactly, so sigma = 2 doubles
+    every output bit for bit."""
+    a = gen(256, R=2, streams=2)
+    b = O.Generator(2, pool_n=256, R=2, stddev=2.0)
+    b.seed(1)
+    ya = a.fill([0, 1], [5000, 3000])
+    yb = b.fill([0, 1], [5000, 3000])
+    np.testing.assert_array_equal(yb, 2 * ya)
+
+
+def test_mean_and_stddev_moments():
+    N = 1 << 20
+    g = O.Generator(4, pool_n=1024, R=2, mean=-3.5, stddev=0.25)
+    g.seed(1)
+    y = g.fill(np.arange(4), [N // 4] * 4).astype(np.float64)
+    m, v, sk, ku = moments(y)
+    assert abs(m + 3.5) < 5 * 0.25 / math.sqrt(N)
+    assert abs(v / 0.0625 - 1) < 5 * math.sqrt(2 / N)
+    assert abs(ku - 3) < 5 * math.sqrt(24 / N)
+
+
+def test_zero_mean_unit_stddev_is_the_plain_generator():
+    a = gen(512, R=2, streams=3)
+    b = O.Generator(3, pool_n=512, R=2, mean=0.0, stddev=1.0)
+    b.seed(1)
+    np.testing.assert_array_equal(a.fill([0, 2], [4000, 7]).view(np.uint32),
+                                  b.fill([0, 2], [4000, 7]).view(np.uint32))
+
+
+def test_current_pool_source_is_fastnorms_choice():
+    a = O.Generator(2, pool_n=256, R=1, x_current=True)
+    b = O.Generator(2, pool_n=256, R=1, hazard=O.HAZ_CURRENT_X)
+    a.seed(4)
+    b.seed(4)
+    np.testing.assert_array_equal(a.fill([0, 1], [9000, 9000]), b.fill([0, 1], [9000, 9000]))
