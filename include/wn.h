@@ -114,6 +114,11 @@ typedef struct {
   uint32_t wgs_per_cu;         /* persistent launches: workgroups per compute unit
                                   (0 = as many as can be resident), <= 16 */
   uint32_t use_graph;          /* 1: persistent launches replay a captured HIP graph */
+  uint32_t long_priority_pct;  /* persistent launches: 0 = off; else the items whose estimated
+                                  work (pools x pool size) is at least this percentage of the
+                                  longest item's run at raised wave priority, so that the
+                                  longest streams (the critical path) keep their pace while
+                                  they share compute units; <= 100 (default 25) */
 } wn_tuning;
 
 /* Validate cfg, select the device, allocate the per-stream state in device
@@ -194,8 +199,9 @@ wn_status wn_get_stream(wn_gen *g, uint32_t s, wn_stream_info *info, void *pool_
  * struct (WN_EINVAL on a bad size, a flag other than 0/1, waves_per_simd other
  * than 0/5/6/8 or set with nontemporal_stores, or wgs_per_cu > 16) and applies
  * to later calls.  Binary32 pools of
- * 1024..8192 values have every choice; other shapes ignore them.  Defaults:
- * the choices measured fastest for binary32 pools on MI355X. */
+ * 1024..8192 values have every choice; other shapes, and the plane-rotation
+ * family (one launch variant), ignore them.  Defaults: the choices measured
+ * fastest for binary32 pools on MI355X. */
 wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t);
 wn_status wn_get_tuning(wn_gen *g, wn_tuning *t);
 

@@ -103,7 +103,7 @@ struct PersistentSlot {
   bool pending = false;
   hipGraphExec_t exec = nullptr;
   // key of the cached graph
-  uint32_t k_nitems = 0, k_dtype = 0, k_variant = 0, k_grid = 0, k_max_n = 0;
+  uint32_t k_nitems = 0, k_dtype = 0, k_variant = 0, k_grid = 0, k_max_n = 0, k_prio = 0;
   void *k_out = nullptr;
 };
 
@@ -136,6 +136,7 @@ struct wn_gen {
   // launch choices (wn_tuning); defaults: LDS double buffer, graph replay
   uint32_t variant = 1;
   uint32_t wgs_per_cu = 0;
+  uint32_t long_priority_pct = 25;
   bool use_graph = true;
   // persistent launches: two staging/work-list slots, each with a cached graph
   PersistentSlot pslots[2];
@@ -483,8 +484,9 @@ hipError_t reserve(wn::WorkItem **host, wn::WorkItem **dev, size_t *cap, size_t 
 // first, to slot.host[0 .. nitems): replays the slot's graph when the launch
 // shape is unchanged, captures a new one otherwise (or launches directly when
 // graphs are off).
-hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, uint32_t max_n,
-                             void *out, uint32_t dtype, wn::StatsOut *stats, hipStream_t st) {
+hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, uint32_t prio_items,
+                             uint32_t max_n, void *out, uint32_t dtype, wn::StatsOut *stats,
+                             hipStream_t st) {
   wn::FillArgs a;
   a.c = common(g, 0);
   a.items = slot.dev;
@@ -494,6 +496,7 @@ hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, u
   a.out = out;
   a.variant = g->variant;
   a.counter = slot.counter;
+  a.prio_items = prio_items;
   a.partials = stats ? g->d_partials : nullptr;
   a.stats = stats;
   int dev = 0, cus = 256;
@@ -509,7 +512,7 @@ hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, u
   }
   const bool hit = slot.exec && slot.k_nitems == nitems && slot.k_dtype == dtype &&
                    slot.k_variant == g->variant && slot.k_grid == grid && slot.k_max_n == max_n &&
-                   slot.k_out == out;
+                   slot.k_out == out && slot.k_prio == prio_items;
   if (!hit) {
     if (slot.exec) {
       (void)hipGraphExecDestroy(slot.exec);
@@ -537,6 +540,7 @@ hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, u
     slot.k_grid = grid;
     slot.k_max_n = max_n;
     slot.k_out = out;
+    slot.k_prio = prio_items;
   }
   return hipGraphLaunch(slot.exec, st);
 }
@@ -622,8 +626,13 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
       const uint32_t j = order[i].second;
       slot.host[i] = wn::WorkItem{streams[j], j, counts[j], off[j]};
     }
-    if ((e = launch_persistent(g, slot, nbig, max_n, out, uint32_t(out_dtype), stats, st)) !=
-        hipSuccess)
+    uint32_t prio_items = 0;
+    if (g->long_priority_pct > 0) {
+      const uint64_t cut = order[0].first * g->long_priority_pct / 100;
+      while (prio_items < nbig && order[prio_items].first >= cut) ++prio_items;
+    }
+    if ((e = launch_persistent(g, slot, nbig, prio_items, max_n, out, uint32_t(out_dtype), stats,
+                               st)) != hipSuccess)
       return hip_fail(e, "wn_fill: persistent launch");
     if ((e = hipEventRecord(slot.done, st)) != hipSuccess) return hip_fail(e, "wn_fill: event");
     slot.pending = true;
@@ -793,12 +802,14 @@ wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t) {
   const uint32_t w = t->waves_per_simd;
   const uint32_t wcode = w == 0 ? 0u : w == 8 ? 1u : w == 6 ? 2u : w == 5 ? 3u : 4u;
   if (t->lds_double_buffer > 1 || t->nontemporal_stores > 1 || wcode > 3 || t->use_graph > 1 ||
-      (wcode && t->nontemporal_stores) || t->wgs_per_cu > 16)
+      (wcode && t->nontemporal_stores) || t->wgs_per_cu > 16 || t->long_priority_pct > 100)
     return fail(WN_EINVAL, "wn_set_tuning: flags must be 0 or 1, waves_per_simd 0/5/6/8 and "
-                           "not with nontemporal_stores, wgs_per_cu <= 16");
+                           "not with nontemporal_stores, wgs_per_cu <= 16, "
+                           "long_priority_pct <= 100");
   g->variant = t->lds_double_buffer | (t->nontemporal_stores << 1) | (wcode << 2);
   g->wgs_per_cu = t->wgs_per_cu;
   g->use_graph = t->use_graph != 0;
+  g->long_priority_pct = t->long_priority_pct;
   return WN_OK;
 }
 
@@ -811,6 +822,7 @@ wn_status wn_get_tuning(wn_gen *g, wn_tuning *t) {
   t->waves_per_simd = kWaves[(g->variant >> 2) & 3u];
   t->wgs_per_cu = g->wgs_per_cu;
   t->use_graph = g->use_graph ? 1u : 0u;
+  t->long_priority_pct = g->long_priority_pct;
   return WN_OK;
 }
 
@@ -837,22 +849,24 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
     affine = streams[j] == streams[0] + j && counts[j] == counts[0] &&
              g->pool_n[streams[j]] == g->pool_n[streams[0]];
   std::vector<wn_tuning> cands;
-  auto add = [&](uint32_t db, uint32_t nt, uint32_t oc, uint32_t wpc) {
+  auto add = [&](uint32_t db, uint32_t nt, uint32_t oc, uint32_t wpc, uint32_t prio) {
     wn_tuning t = cur;
     t.lds_double_buffer = db;
     t.nontemporal_stores = nt;
     t.waves_per_simd = oc;
     t.wgs_per_cu = wpc;
+    t.long_priority_pct = prio;
     cands.push_back(t);
   };
   if (affine) {
     for (uint32_t db = 0; db < 2; ++db)
-      for (uint32_t wps : {0u, 5u, 6u, 8u}) add(db, 0, wps, cur.wgs_per_cu);
-    add(1, 1, 0, cur.wgs_per_cu);
+      for (uint32_t wps : {0u, 5u, 6u, 8u}) add(db, 0, wps, cur.wgs_per_cu, cur.long_priority_pct);
+    add(1, 1, 0, cur.wgs_per_cu, cur.long_priority_pct);
   } else {
-    for (uint32_t db = 0; db < 2; ++db)
-      for (uint32_t wpc : {0u, 2u, 3u, 4u, 6u, 8u}) add(db, 0, 0, wpc);
-    add(1, 1, 0, 0);
+    for (uint32_t prio : {0u, 10u, 25u})
+      for (uint32_t db = 0; db < 2; ++db)
+        for (uint32_t wpc : {0u, 3u, 4u, 6u}) add(db, 0, 0, wpc, prio);
+    add(1, 1, 0, 0, 25);
   }
 
   // snapshot of the state, restored after every candidate

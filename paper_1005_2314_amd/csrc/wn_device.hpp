@@ -119,10 +119,11 @@ __device__ __forceinline__ PassParams decode_rotation(uint64_t u1, uint64_t u2, 
   return p;
 }
 
-// the pass parameters of the configured transform for pool rows of length L = n/4
-__device__ __forceinline__ PassParams decode_for(uint32_t transform, uint64_t u1, uint64_t u2,
-                                                 uint32_t L) {
-  return transform ? decode_rotation(u1, u2, 2 * L) : decode(u1, u2, L);
+// the pass parameters of the transform family for pool rows of length L = n/4
+template <bool ROT>
+__device__ __forceinline__ PassParams decode_for(uint64_t u1, uint64_t u2, uint32_t L) {
+  if constexpr (ROT) return decode_rotation(u1, u2, 2 * L);
+  return decode(u1, u2, L);
 }
 
 // ---- the 4x4 transform (Section 5.3) -----------------------------------------
@@ -456,15 +457,20 @@ struct Engine {
       for (int h = 0; h < 2; ++h) rotate(cT, sT, x[c][h], x[c][h + 2], y[c][h], y[c][h + 2]);
   }
 
-  template <int RB>
+  // ROT (compile-time, so that each family's kernels carry only their own
+  // gather): a rotation pass; otherwise A_{k+1} by the runtime k.
+  template <int RB, bool ROT>
   __device__ __forceinline__ void pass_from(const PassParams &p, bool renorm, double g) {
     constexpr int WB = DB ? 1 - RB : RB;
-    switch (p.k) {
-      case kRotation: gather_rotate<RB>(p, renorm, g); break;
-      case 0: gather_transform<0, RB>(p, renorm, g); break;
-      case 1: gather_transform<1, RB>(p, renorm, g); break;
-      case 2: gather_transform<2, RB>(p, renorm, g); break;
-      default: gather_transform<3, RB>(p, renorm, g); break;
+    if constexpr (ROT) {
+      gather_rotate<RB>(p, renorm, g);
+    } else {
+      switch (p.k) {
+        case 0: gather_transform<0, RB>(p, renorm, g); break;
+        case 1: gather_transform<1, RB>(p, renorm, g); break;
+        case 2: gather_transform<2, RB>(p, renorm, g); break;
+        default: gather_transform<3, RB>(p, renorm, g); break;
+      }
     }
     if (!DB) __syncthreads();
     T *W = buf(WB);
@@ -479,11 +485,12 @@ struct Engine {
   // applies the renormalisation scale g to every gathered value first (each
   // element is gathered exactly once per pass, so this equals rescaling the
   // whole pool before the pass).
+  template <bool ROT>
   __device__ __forceinline__ void pass(const PassParams &p, bool renorm, double g) {
     if (DB && cb != 0) {
-      pass_from<1>(p, renorm, g);
+      pass_from<1, ROT>(p, renorm, g);
     } else {
-      pass_from<0>(p, renorm, g);
+      pass_from<0, ROT>(p, renorm, g);
     }
     if (DB) cb ^= 1u;
   }
@@ -561,16 +568,17 @@ struct Engine {
 
   // Emit pool positions [lo, hi) scaled by fT to out[obase + (i - lo)]; with
   // STATS, also accumulate each emitted value into `sa`.
-  // T(P[i] * fT), plus muT in the pool type when has_mu
-  __device__ __forceinline__ static T scaled(T v, T fT, bool has_mu, T muT) {
+  // T(P[i] * fT), plus muT in the pool type when MU
+  template <bool MU>
+  __device__ __forceinline__ static T scaled(T v, T fT, T muT) {
     const T y = v * fT;
-    return has_mu ? T(y + muT) : y;
+    if constexpr (MU) return T(y + muT);
+    return y;
   }
 
-  template <bool NT, bool STATS, typename O>
+  template <bool NT, bool STATS, bool MU, typename O>
   __device__ __forceinline__ void emit(O *__restrict__ out, uint64_t obase, uint32_t lo,
-                                       uint32_t hi, T fT, StatsAcc *sa, bool has_mu = false,
-                                       T muT = T(0)) const {
+                                       uint32_t hi, T fT, StatsAcc *sa, T muT) const {
     const uint32_t L = len();
     if (lo == 0 && hi == 4 * L - 1) {
       // a whole pool: every position but the withheld last one
@@ -579,7 +587,7 @@ struct Engine {
       for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int c = 0; c < NQ; ++c) {
-          const O v = Cast<O>::from(scaled(y[c][m], fT, has_mu, muT));
+          const O v = Cast<O>::from(scaled<MU>(y[c][m], fT, muT));
           if (m < 3 || c < NQ - 1 || tid < bd() - 1) {
             put<NT>(dst + (uint32_t(m) * L + uint32_t(c) * bd()), v);
             if constexpr (STATS) sa->add(widen(v));
@@ -593,7 +601,7 @@ struct Engine {
       for (int c = 0; c < NQ; ++c) {
         const uint32_t i = pos(m, c);
         if (i >= lo && i < hi) {
-          const O v = Cast<O>::from(scaled(y[c][m], fT, has_mu, muT));
+          const O v = Cast<O>::from(scaled<MU>(y[c][m], fT, muT));
           put<NT>(out + (obase + (i - lo)), v);
           if constexpr (STATS) sa->add(widen(v));
         }
@@ -672,7 +680,7 @@ __device__ __forceinline__ void hist_flush(uint32_t *hist, StatsOut *out) {
 }
 
 // ---- seeding (Section 5.8: the uniform source initialises the pool) ----------------
-template <typename T, int NQ, bool SMALL>
+template <typename T, int NQ, bool SMALL, bool ROT>
 __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t s = a.streams[blockIdx.x];
@@ -704,7 +712,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
   for (uint32_t w = 0; w < a.warmup; ++w) {
     const uint64_t u1 = xs_next(xs);
     const uint64_t u2 = xs_next(xs);
-    e.pass(decode_for(a.c.transform, u1, u2, e.len()), false, 1.0);
+    e.template pass<ROT>(decode_for<ROT>(u1, u2, e.len()), false, 1.0);
     __syncthreads();
   }
   Q = e.sumsq();
@@ -737,7 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
 // the withheld value f * P[n-1] feeds the next sample.  The stored pool is
 // never scaled.  Starts and ends without a barrier of its own: the caller
 // separates two items on one workgroup by a barrier.
-template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, bool STATS = false>
+template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, bool STATS, bool ROT>
 __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem, uint32_t s,
                                           uint64_t count, uint64_t obase, uint32_t req = 0) {
   StreamHdr *h = a.c.hdr + s;
@@ -773,8 +781,11 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   const T muT = T(a.c.mu);
   if (cursor < n - 1) {
     const uint32_t take = take_of(count, n - 1 - cursor);
-    e.template emit<NT, STATS>(out, obase, cursor, cursor + take, T(__dmul_rn(f, a.c.sigma)), &sa,
-                               has_mu, muT);
+    const T fT = T(__dmul_rn(f, a.c.sigma));
+    if (has_mu)
+      e.template emit<NT, STATS, true>(out, obase, cursor, cursor + take, fT, &sa, muT);
+    else
+      e.template emit<NT, STATS, false>(out, obase, cursor, cursor + take, fT, &sa, muT);
     obase += take;
     count -= take;
     cursor += take;
@@ -787,7 +798,7 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     for (uint32_t r = 0; r < a.c.R; ++r) {
       const uint64_t u1 = xs_next(xs);
       const uint64_t u2 = xs_next(xs);
-      e.pass(decode_for(a.c.transform, u1, u2, e.len()), renorm && r == 0, g);
+      e.template pass<ROT>(decode_for<ROT>(u1, u2, e.len()), renorm && r == 0, g);
       if (r + 1 < a.c.R) __syncthreads();
     }
     const double Q = e.sumsq();
@@ -822,7 +833,11 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     }
     k += 1;
     const uint32_t take = take_of(count, n - 1);
-    e.template emit<NT, STATS>(out, obase, 0, take, T(__dmul_rn(f, a.c.sigma)), &sa, has_mu, muT);
+    const T fT = T(__dmul_rn(f, a.c.sigma));
+    if (has_mu)
+      e.template emit<NT, STATS, true>(out, obase, 0, take, fT, &sa, muT);
+    else
+      e.template emit<NT, STATS, false>(out, obase, 0, take, fT, &sa, muT);
     obase += take;
     count -= take;
     cursor = take;
@@ -870,7 +885,8 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
 }
 
 // One workgroup per work item (all items of the launch share one pool size).
-template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE, bool STATS = false>
+template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE, bool STATS,
+          bool ROT>
 __global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t j = blockIdx.x;
@@ -892,19 +908,19 @@ __global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
     return;
   }
   const uint32_t req = a.items ? a.items[j].req : j;
-  fill_item<T, O, NQ, SMALL, DB, NT, STATS>(a, smem, s, count, obase, req);
+  fill_item<T, O, NQ, SMALL, DB, NT, STATS, ROT>(a, smem, s, count, obase, req);
 }
 
-template <typename T, typename O, int NQ, int MAXNQ, bool DB, bool NT, bool STATS>
+template <typename T, typename O, int NQ, int MAXNQ, bool DB, bool NT, bool STATS, bool ROT>
 __device__ __forceinline__ void item_as(const FillArgs &a, unsigned char *smem, const WorkItem &it) {
-  fill_item<T, O, NQ, false, DB, NT, STATS>(a, smem, it.stream, it.count, it.out_off, it.req);
+  fill_item<T, O, NQ, false, DB, NT, STATS, ROT>(a, smem, it.stream, it.count, it.out_off, it.req);
 }
 
 // Persistent form: a fixed grid of workgroups pops work items (pool sizes
 // 1024 .. 1024*MAXNQ, mixed) from a device counter in the order of the list
 // (the host sorts it longest first).  Every workgroup leaves the loop once the
 // counter passes the end of the list.
-template <typename T, typename O, int MAXNQ, bool DB, bool NT, bool STATS = false>
+template <typename T, typename O, int MAXNQ, bool DB, bool NT, bool STATS, bool ROT>
 __global__ __launch_bounds__(kBlock) void k_fill_persistent(FillArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   // the last 8 bytes of the allocation: the largest pool's spare broadcast
@@ -917,6 +933,12 @@ __global__ __launch_bounds__(kBlock) void k_fill_persistent(FillArgs a) {
     __syncthreads();
     const uint32_t j = uint32_t(next_item);
     if (j >= a.nitems) break;
+    // the list is longest first: its head is the critical path, so its waves
+    // win instruction issue against the shorter items sharing the SIMD
+    if (j < a.prio_items)
+      __builtin_amdgcn_s_setprio(3);
+    else
+      __builtin_amdgcn_s_setprio(0);
     const WorkItem it = a.items[j];
     if (it.count == 0) {
       if constexpr (STATS)
@@ -924,11 +946,11 @@ __global__ __launch_bounds__(kBlock) void k_fill_persistent(FillArgs a) {
       continue;
     }
     switch (a.c.hdr[it.stream].n) {
-      case 1024: item_as<T, O, 1, MAXNQ, DB, NT, STATS>(a, smem, it); break;
-      case 2048: if constexpr (MAXNQ >= 2) item_as<T, O, 2, MAXNQ, DB, NT, STATS>(a, smem, it); break;
-      case 4096: if constexpr (MAXNQ >= 4) item_as<T, O, 4, MAXNQ, DB, NT, STATS>(a, smem, it); break;
-      case 8192: if constexpr (MAXNQ >= 8) item_as<T, O, 8, MAXNQ, DB, NT, STATS>(a, smem, it); break;
-      default: if constexpr (MAXNQ >= 16) item_as<T, O, 16, MAXNQ, DB, NT, STATS>(a, smem, it); break;
+      case 1024: item_as<T, O, 1, MAXNQ, DB, NT, STATS, ROT>(a, smem, it); break;
+      case 2048: if constexpr (MAXNQ >= 2) item_as<T, O, 2, MAXNQ, DB, NT, STATS, ROT>(a, smem, it); break;
+      case 4096: if constexpr (MAXNQ >= 4) item_as<T, O, 4, MAXNQ, DB, NT, STATS, ROT>(a, smem, it); break;
+      case 8192: if constexpr (MAXNQ >= 8) item_as<T, O, 8, MAXNQ, DB, NT, STATS, ROT>(a, smem, it); break;
+      default: if constexpr (MAXNQ >= 16) item_as<T, O, 16, MAXNQ, DB, NT, STATS, ROT>(a, smem, it); break;
     }
   }
 }

@@ -20,10 +20,10 @@ hipError_t prepare(Kern kern, size_t lds) {
   return hipSuccess;
 }
 
-template <int NQ, bool SMALL>
+template <int NQ, bool SMALL, bool ROT = false>
 hipError_t seed_t(const SeedArgs &a, hipStream_t st) {
   const size_t lds = lds_bytes(a.c.n, false);
-  auto kern = k_seed<T, NQ, SMALL>;
+  auto kern = k_seed<T, NQ, SMALL, ROT>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
   const uint32_t block = SMALL ? a.c.n / 4 : kBlock;
@@ -31,10 +31,11 @@ hipError_t seed_t(const SeedArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE = 1, bool STATS = false>
+template <typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE = 1, bool STATS = false,
+          bool ROT = false>
 hipError_t fill_t(const FillArgs &a, hipStream_t st) {
   const size_t lds = lds_bytes(a.c.n, DB, STATS);
-  auto kern = k_fill<T, O, NQ, SMALL, DB, NT, WPE, STATS>;
+  auto kern = k_fill<T, O, NQ, SMALL, DB, NT, WPE, STATS, ROT>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
   const uint32_t block = SMALL ? a.c.n / 4 : kBlock;
@@ -47,6 +48,11 @@ hipError_t fill_t(const FillArgs &a, hipStream_t st) {
 // 8, 6 or 5 waves per SIMD.
 template <typename O, int NQ>
 hipError_t fill_v(const FillArgs &a, hipStream_t st) {
+  if (a.c.transform) {  // plane rotations: one launch variant, tuning choices ignored
+    constexpr bool db = NQ <= 8;
+    if (a.partials) return fill_t<O, NQ, false, db, false, 1, true, true>(a, st);
+    return fill_t<O, NQ, false, db, false, 1, false, true>(a, st);
+  }
   if (a.partials) {  // fused statistics: one variant (two LDS buffers where they fit)
     if constexpr (NQ <= 8) return fill_t<O, NQ, false, true, false, 1, true>(a, st);
     return fill_t<O, NQ, false, false, false, 1, true>(a, st);
@@ -68,10 +74,10 @@ hipError_t fill_v(const FillArgs &a, hipStream_t st) {
   return fill_t<O, NQ, false, false, false>(a, st);
 }
 
-template <typename O, int MAXNQ, bool DB, bool NT, bool STATS = false>
+template <typename O, int MAXNQ, bool DB, bool NT, bool STATS = false, bool ROT = false>
 hipError_t persistent_t(const FillArgs &a, uint32_t grid, hipStream_t st) {
   const size_t lds = lds_bytes(1024u * MAXNQ, DB, STATS);
-  auto kern = k_fill_persistent<T, O, MAXNQ, DB, NT, STATS>;
+  auto kern = k_fill_persistent<T, O, MAXNQ, DB, NT, STATS, ROT>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
   if (grid == 0) {  // as many workgroups as can be resident at once
@@ -94,6 +100,10 @@ template <typename O, int MAXNQ>
 hipError_t persistent_v(const FillArgs &a, uint32_t grid, hipStream_t st) {
   static_assert(lds_bytes_for<T>(1024 * MAXNQ, true, true) <= kMaxLds,
                 "two binary32 pool buffers and the statistics fit in LDS");
+  if (a.c.transform) {
+    if (a.partials) return persistent_t<O, MAXNQ, true, false, true, true>(a, grid, st);
+    return persistent_t<O, MAXNQ, true, false, false, true>(a, grid, st);
+  }
   if (a.partials) return persistent_t<O, MAXNQ, true, false, true>(a, grid, st);
   switch (a.variant & 3u) {
     case 1: return persistent_t<O, MAXNQ, true, false>(a, grid, st);
@@ -109,15 +119,20 @@ hipError_t persistent_n(const FillArgs &a, uint32_t max_n, uint32_t grid, hipStr
   return persistent_v<O, 16>(a, grid, st);
 }
 
-hipError_t seed_n(const SeedArgs &a, hipStream_t st) {
+template <bool ROT>
+hipError_t seed_r(const SeedArgs &a, hipStream_t st) {
   switch (a.c.n) {
-    case 1024: return seed_t<1, false>(a, st);
-    case 2048: return seed_t<2, false>(a, st);
-    case 4096: return seed_t<4, false>(a, st);
-    case 8192: return seed_t<8, false>(a, st);
-    case 16384: return seed_t<16, false>(a, st);
-    default: return seed_t<1, true>(a, st);
+    case 1024: return seed_t<1, false, ROT>(a, st);
+    case 2048: return seed_t<2, false, ROT>(a, st);
+    case 4096: return seed_t<4, false, ROT>(a, st);
+    case 8192: return seed_t<8, false, ROT>(a, st);
+    case 16384: return seed_t<16, false, ROT>(a, st);
+    default: return seed_t<1, true, ROT>(a, st);
   }
+}
+
+hipError_t seed_n(const SeedArgs &a, hipStream_t st) {
+  return a.c.transform ? seed_r<true>(a, st) : seed_r<false>(a, st);
 }
 
 template <typename O>
@@ -129,6 +144,10 @@ hipError_t fill_n(const FillArgs &a, hipStream_t st) {
     case 8192: return fill_v<O, 8>(a, st);
     case 16384: return fill_v<O, 16>(a, st);
     default:
+      if (a.c.transform) {
+        if (a.partials) return fill_t<O, 1, true, false, false, 1, true, true>(a, st);
+        return fill_t<O, 1, true, false, false, 1, false, true>(a, st);
+      }
       if (a.partials) return fill_t<O, 1, true, false, false, 1, true>(a, st);
       return fill_t<O, 1, true, false, false>(a, st);
   }

@@ -181,11 +181,13 @@ def test_tuning_variants_bit_exact(db, nt, oc, n, out):
 
 def test_tuning_rejects_bad_values():
     g = W.Generator(2, pool_n=64, R=1)
-    t = g.tuning()
-    t.lds_double_buffer = 2
-    with pytest.raises(W.WnError) as ei:
-        W.check(W.load().wn_set_tuning(g._h, W.C.byref(t)))
-    assert ei.value.status == W.WN_EINVAL
+    for field, value in (("lds_double_buffer", 2), ("long_priority_pct", 101),
+                         ("waves_per_simd", 7), ("wgs_per_cu", 17)):
+        t = g.tuning()
+        setattr(t, field, value)
+        with pytest.raises(W.WnError) as ei:
+            W.check(W.load().wn_set_tuning(g._h, W.C.byref(t)))
+        assert ei.value.status == W.WN_EINVAL, field
 
 
 def _request(rng, ns, max_count):
@@ -195,11 +197,12 @@ def _request(rng, ns, max_count):
 
 
 @pytest.mark.parametrize("use_graph", [0, 1])
-@pytest.mark.parametrize("wgs", [0, 1, 3])
-def test_persistent_launch_shapes_bit_exact(use_graph, wgs):
+@pytest.mark.parametrize("wgs,prio", [(0, 0), (1, 0), (3, 0), (0, 50), (3, 100), (1, 1)])
+def test_persistent_launch_shapes_bit_exact(use_graph, wgs, prio):
     sizes = np.array([1024, 2048, 4096] * 7, np.uint32)
     p = Pair(len(sizes), pool_n=sizes, R=2, seed=13)
-    p.gpu.set_tuning(use_graph=use_graph, wgs_per_cu=wgs)
+    p.gpu.set_tuning(use_graph=use_graph, wgs_per_cu=wgs, long_priority_pct=prio)
+    assert p.gpu.tuning().long_priority_pct == prio
     rng = np.random.default_rng(wgs)
     order, counts = _request(rng, len(sizes), 20000)
     for call in range(3):  # the same shape again: the cached graph is replayed
