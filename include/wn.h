@@ -151,8 +151,9 @@ wn_status wn_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint6
  * y is each value as stored in the output type.  For every pool k produced,
  * D_k = f_k^2 (Q_k - P_k[n-1]^2) - (n - 1) is the sum of squares of its n-1
  * emitted values (Section 5.5) minus its expected value; successive pools of a
- * stream (also across calls) form the lag pairs used to detect pool-to-pool
- * correlation (Sections 5.6, 5.7).  Centring keeps the lag-1 correlation
+ * stream form the lag pairs used to detect pool-to-pool correlation (Sections
+ * 5.6, 5.7), also across calls, as long as both pools were produced by
+ * wn_fill_stats (a wn_fill that produces a pool starts a new chain).  Centring keeps the lag-1 correlation
  * (t_lag/t_pairs - (t_sum/pools)^2) / variance well conditioned. */
 typedef struct {
   uint64_t count;        /* values emitted */

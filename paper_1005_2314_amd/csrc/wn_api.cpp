@@ -160,6 +160,7 @@ wn::KernelCommon common(const wn_gen *g, uint32_t n) {
   c.x_current = g->x_current;
   c.has_mu = g->mean != 0.0;
   c.transform = g->transform;
+  c.unit_sigma = g->stddev == 1.0 ? 1u : 0u;
   c.sigma = g->stddev;
   c.mu = g->mean;
   for (int i = 0; i < wn::kNumSizes; ++i) {

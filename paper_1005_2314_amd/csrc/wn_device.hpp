@@ -731,7 +731,8 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
     h->xnext = last;
     h->qlast = Q;
     h->n = n;
-    h->cursor = n - 1;
+    h->cursor = uint16_t(n - 1);
+    h->sflags = 0;
   }
 }
 
@@ -754,7 +755,9 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   StatsAcc sa;
   double t_sum = 0.0, t_sumsq = 0.0, t_lag = 0.0, tprev = 0.0;
   uint64_t pools = 0, t_pairs = 0, x_pools = 0, x_pairs = 0;
-  uint32_t xprev = 0;
+  const uint32_t sflags = h->sflags;
+  bool prev_seen = (sflags & kSeenByStats) != 0;  // may the next pool pair with the current?
+  uint32_t xprev = sflags & kHeldExtreme;
   uint32_t *xflags = nullptr;
   const uint64_t emitted = count;
   if constexpr (STATS) {
@@ -762,11 +765,11 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     xflags = stats_flags(smem, size_t(n) * sizeof(T) * (DB ? 2 : 1));
     hist_clear(sa.hist);  // published by the barrier after the pool load
     tprev = h->tprev;
-    xprev = h->xprev;
   }
   const Chi2Consts &cc = a.c.cc[__builtin_ctz(n) - 4];
   uint64_t xs = h->xs;
   uint64_t k = h->k;
+  const uint64_t k0 = k;
   double f = h->f;
   double xnext = h->xnext;
   double qlast = h->qlast;
@@ -777,11 +780,16 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   e.load_global(gpool);
   __syncthreads();
 
-  const bool has_mu = a.c.has_mu != 0;
+  // Options as wave-uniform scalars, so that each costs one scalar branch
+  // per pool rather than vector selects (the defaults skip their work).
+  const bool has_mu = __builtin_amdgcn_readfirstlane(a.c.has_mu) != 0;
+  const bool unit_sigma = __builtin_amdgcn_readfirstlane(a.c.unit_sigma) != 0;
+  const bool x_current = __builtin_amdgcn_readfirstlane(a.c.x_current) != 0;
   const T muT = T(a.c.mu);
+  auto scale_of = [&](double fk) -> T { return unit_sigma ? T(fk) : T(__dmul_rn(fk, a.c.sigma)); };
   if (cursor < n - 1) {
     const uint32_t take = take_of(count, n - 1 - cursor);
-    const T fT = T(__dmul_rn(f, a.c.sigma));
+    const T fT = scale_of(f);
     if (has_mu)
       e.template emit<NT, STATS, true>(out, obase, cursor, cursor + take, fT, &sa, muT);
     else
@@ -804,8 +812,11 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     const double Q = e.sumsq();
     const double last = double(e.last());
     double fk = 1.0;
-    if (a.c.chi2 != kChi2Off)
-      fk = __dsqrt_rn(__ddiv_rn(chi2_sample(cc, a.c.chi2, a.c.x_current ? last : xnext), Q));
+    if (a.c.chi2 != kChi2Off) {
+      double x_src = xnext;
+      if (x_current) x_src = last;
+      fk = __dsqrt_rn(__ddiv_rn(chi2_sample(cc, a.c.chi2, x_src), Q));
+    }
     if (e.tid == 0) flag_fault(a.c.err, Q);
     f = fk;
     xnext = __dmul_rn(fk, last);
@@ -817,7 +828,8 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
                                   double(n - 1));
       t_sum = __dadd_rn(t_sum, Tk);
       t_sumsq = __dadd_rn(t_sumsq, __dmul_rn(Tk, Tk));
-      if (k > 0) {
+      const bool paired = k > 0 && prev_seen;
+      if (paired) {
         t_lag = __dadd_rn(t_lag, __dmul_rn(Tk, tprev));
         t_pairs += 1;
       }
@@ -828,12 +840,13 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
       const T zmax = T(e.max_abs_emitted() * T(fk));
       const uint32_t ek = e.block_any(double(zmax) >= a.c.xthr[__builtin_ctz(n) - 4], xflags);
       x_pools += ek;
-      if (k > 0) x_pairs += ek & xprev;
+      if (paired) x_pairs += ek & xprev;
       xprev = ek;
+      prev_seen = true;
     }
     k += 1;
     const uint32_t take = take_of(count, n - 1);
-    const T fT = T(__dmul_rn(f, a.c.sigma));
+    const T fT = scale_of(f);
     if (has_mu)
       e.template emit<NT, STATS, true>(out, obase, 0, take, fT, &sa, muT);
     else
@@ -850,10 +863,12 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     h->f = f;
     h->xnext = xnext;
     h->qlast = qlast;
-    h->cursor = cursor;
+    h->cursor = uint16_t(cursor);
     if constexpr (STATS) {
       h->tprev = tprev;
-      h->xprev = xprev;
+      if (pools > 0) h->sflags = uint16_t(kSeenByStats | xprev);
+    } else if (sflags != 0 && k != k0) {
+      h->sflags = 0;  // a pool the statistics did not see
     }
   }
   if constexpr (STATS) {

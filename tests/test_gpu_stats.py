@@ -187,3 +187,33 @@ def test_extreme_pools_cluster_at_full_size():
             assert (st.x_pairs - expected) / math.sqrt(expected) > 10
         del out
     assert ratios[1] - 1 < 0.5 * (ratios[0] - 1)
+
+
+def test_pairs_join_only_pools_the_statistics_saw():
+    """Lag pairs span calls, but a plain fill that produces pools breaks the
+    chain; one that only drains the current pool does not."""
+    n, ns = 1024, 3
+    gpu = W.Generator(ns, pool_n=n, R=2)
+    orc = O.Generator(ns, pool_n=n, R=2, trace=True)
+    gpu.seed(21)
+    orc.seed(21)
+    streams = np.arange(ns)
+    _, a = run(gpu, streams, [3 * (n - 1) + 5] * ns)          # 4 pools each
+    orc.fill(streams, [3 * (n - 1) + 5] * ns)
+    assert a.pools == 4 * ns and a.t_pairs == 3 * ns
+    gpu.fill(streams, [10] * ns)                                # drains, no new pool
+    orc.fill(streams, [10] * ns)
+    _, b = run(gpu, streams, [2 * (n - 1)] * ns)                # 2 pools each, chained
+    orc.fill(streams, [2 * (n - 1)] * ns)
+    assert b.pools == 2 * ns and b.t_pairs == 2 * ns
+    gpu.fill(streams, [n] * ns)                                 # produces pools: chain broken
+    orc.fill(streams, [n] * ns)
+    _, c = run(gpu, streams, [3 * (n - 1)] * ns)
+    assert c.pools == 3 * ns and c.t_pairs == 2 * ns
+    # the extreme-pool pairs follow the same chain: recount from the oracle
+    thr = O.extreme_threshold(n)
+    want = 0
+    for s_ in streams:
+        e = orc.trace(int(s_))[:, 5] >= thr
+        want += sum(int(e[k] and e[k - 1]) for k in range(len(e) - 2, len(e)))
+    assert c.x_pairs == want
