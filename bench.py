@@ -234,7 +234,8 @@ def main():
                    "pool_n": w["pool_n"], "passes": w["R"], "seed_ms": seed_s * 1e3,
                    "tuning": {"lds_double_buffer": tuned.lds_double_buffer,
                               "nontemporal_stores": tuned.nontemporal_stores,
-                              "waves_per_simd": tuned.waves_per_simd}},
+                              "waves_per_simd": tuned.waves_per_simd,
+                              "streams_per_wg": tuned.streams_per_wg}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_fill (pool 4096 binary32, binary32 output)", "kernel_ms": avg_ms,

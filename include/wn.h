@@ -119,6 +119,9 @@ typedef struct {
                                   longest item's run at raised wave priority, so that the
                                   longest streams (the critical path) keep their pace while
                                   they share compute units; <= 100 (default 25) */
+  uint32_t streams_per_wg;     /* one-size launches of consecutive streams with equal counts:
+                                  each workgroup runs this many streams one after another
+                                  (longer contiguous output runs); 1..16, default 1 */
 } wn_tuning;
 
 /* Validate cfg, select the device, allocate the per-stream state in device
@@ -207,7 +210,8 @@ wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t);
 wn_status wn_get_tuning(wn_gen *g, wn_tuning *t);
 
 /* Autotune the launch choices for one request shape: run the request once per
- * candidate (LDS buffering, store kind, register cap, persistent grid size),
+ * candidate (LDS buffering, store kind, register cap, streams per workgroup;
+ * for persistent launches grid size and long-item priority),
  * timed with HIP events on hip_stream, restoring the generator's state after
  * each run, and keep the fastest.  The generator's state is unchanged on
  * return; `out` (same contract as wn_fill) is used as scratch and holds no

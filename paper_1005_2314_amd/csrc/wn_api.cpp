@@ -137,6 +137,7 @@ struct wn_gen {
   uint32_t variant = 1;
   uint32_t wgs_per_cu = 0;
   uint32_t long_priority_pct = 25;
+  uint32_t streams_per_wg = 1;
   bool use_graph = true;
   // persistent launches: two staging/work-list slots, each with a cached graph
   PersistentSlot pslots[2];
@@ -570,6 +571,7 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
     a.nitems = nreq;
     a.affine_s0 = streams[0];
     a.count_each = counts[0];
+    a.items_per_wg = g->streams_per_wg;
     a.out = out;
     a.variant = g->variant;
     a.counter = nullptr;
@@ -803,14 +805,16 @@ wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t) {
   const uint32_t w = t->waves_per_simd;
   const uint32_t wcode = w == 0 ? 0u : w == 8 ? 1u : w == 6 ? 2u : w == 5 ? 3u : 4u;
   if (t->lds_double_buffer > 1 || t->nontemporal_stores > 1 || wcode > 3 || t->use_graph > 1 ||
-      (wcode && t->nontemporal_stores) || t->wgs_per_cu > 16 || t->long_priority_pct > 100)
+      (wcode && t->nontemporal_stores) || t->wgs_per_cu > 16 || t->long_priority_pct > 100 ||
+      t->streams_per_wg < 1 || t->streams_per_wg > 16)
     return fail(WN_EINVAL, "wn_set_tuning: flags must be 0 or 1, waves_per_simd 0/5/6/8 and "
                            "not with nontemporal_stores, wgs_per_cu <= 16, "
-                           "long_priority_pct <= 100");
+                           "long_priority_pct <= 100, streams_per_wg in [1, 16]");
   g->variant = t->lds_double_buffer | (t->nontemporal_stores << 1) | (wcode << 2);
   g->wgs_per_cu = t->wgs_per_cu;
   g->use_graph = t->use_graph != 0;
   g->long_priority_pct = t->long_priority_pct;
+  g->streams_per_wg = t->streams_per_wg;
   return WN_OK;
 }
 
@@ -824,6 +828,7 @@ wn_status wn_get_tuning(wn_gen *g, wn_tuning *t) {
   t->wgs_per_cu = g->wgs_per_cu;
   t->use_graph = g->use_graph ? 1u : 0u;
   t->long_priority_pct = g->long_priority_pct;
+  t->streams_per_wg = g->streams_per_wg;
   return WN_OK;
 }
 
@@ -850,8 +855,10 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
     affine = streams[j] == streams[0] + j && counts[j] == counts[0] &&
              g->pool_n[streams[j]] == g->pool_n[streams[0]];
   std::vector<wn_tuning> cands;
-  auto add = [&](uint32_t db, uint32_t nt, uint32_t oc, uint32_t wpc, uint32_t prio) {
+  auto add = [&](uint32_t db, uint32_t nt, uint32_t oc, uint32_t wpc, uint32_t prio,
+                 uint32_t spw = 1) {
     wn_tuning t = cur;
+    t.streams_per_wg = spw;
     t.lds_double_buffer = db;
     t.nontemporal_stores = nt;
     t.waves_per_simd = oc;
@@ -860,9 +867,11 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
     cands.push_back(t);
   };
   if (affine) {
-    for (uint32_t db = 0; db < 2; ++db)
-      for (uint32_t wps : {0u, 5u, 6u, 8u}) add(db, 0, wps, cur.wgs_per_cu, cur.long_priority_pct);
-    add(1, 1, 0, cur.wgs_per_cu, cur.long_priority_pct);
+    for (uint32_t spw : {1u, 2u, 4u, 8u})
+      for (uint32_t db = 0; db < 2; ++db)
+        for (uint32_t wps : {0u, 5u, 6u, 8u})
+          add(db, 0, wps, cur.wgs_per_cu, cur.long_priority_pct, spw);
+    add(1, 1, 0, cur.wgs_per_cu, cur.long_priority_pct, 1);
   } else {
     for (uint32_t prio : {0u, 10u, 25u})
       for (uint32_t db = 0; db < 2; ++db)

@@ -899,31 +899,41 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   }
 }
 
-// One workgroup per work item (all items of the launch share one pool size).
+// Workgroup b runs work items b*P .. b*P + P-1 one after another (P =
+// items_per_wg; all items of the launch share one pool size).  In the affine
+// form consecutive items write consecutive output ranges, so a larger P gives
+// each workgroup a longer contiguous run of stores.
 template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE, bool STATS,
           bool ROT>
 __global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t j = blockIdx.x;
-  uint32_t s;
-  uint64_t count, obase;
-  if (a.items) {
-    const WorkItem it = a.items[j];
-    s = it.stream;
-    count = it.count;
-    obase = it.out_off;
-  } else {
-    s = a.affine_s0 + j;
-    count = a.count_each;
-    obase = uint64_t(j) * a.count_each;
+  const uint32_t per = a.items_per_wg;
+  bool ran = false;
+  for (uint32_t t = 0; t < per; ++t) {
+    const uint32_t j = blockIdx.x * per + t;
+    if (j >= a.nitems) break;
+    uint32_t s;
+    uint64_t count, obase;
+    if (a.items) {
+      const WorkItem it = a.items[j];
+      s = it.stream;
+      count = it.count;
+      obase = it.out_off;
+    } else {
+      s = a.affine_s0 + j;
+      count = a.count_each;
+      obase = uint64_t(j) * a.count_each;
+    }
+    if (count == 0) {
+      if constexpr (STATS)
+        if (threadIdx.x == 0) a.partials[j] = StatsPartial{};
+      continue;
+    }
+    if (ran) __syncthreads();  // the previous item's last LDS reads are done
+    ran = true;
+    const uint32_t req = a.items ? a.items[j].req : j;
+    fill_item<T, O, NQ, SMALL, DB, NT, STATS, ROT>(a, smem, s, count, obase, req);
   }
-  if (count == 0) {
-    if constexpr (STATS)
-      if (threadIdx.x == 0) a.partials[j] = StatsPartial{};
-    return;
-  }
-  const uint32_t req = a.items ? a.items[j].req : j;
-  fill_item<T, O, NQ, SMALL, DB, NT, STATS, ROT>(a, smem, s, count, obase, req);
 }
 
 template <typename T, typename O, int NQ, int MAXNQ, bool DB, bool NT, bool STATS, bool ROT>

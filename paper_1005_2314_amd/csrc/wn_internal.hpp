@@ -105,6 +105,7 @@ struct FillArgs {
   uint32_t nitems = 0;
   uint32_t affine_s0 = 0;           // affine form: item j = (s0 + j, count_each, j * count_each)
   uint64_t count_each = 0;
+  uint32_t items_per_wg = 1;        // one-size launches: consecutive items per workgroup
   void *out = nullptr;
   uint32_t variant = 0;             // non-semantic kernel variant (wn_tuning)
   uint32_t *counter = nullptr;      // persistent form: next work item (reset by the launch)

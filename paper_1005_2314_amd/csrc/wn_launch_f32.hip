@@ -39,7 +39,8 @@ hipError_t fill_t(const FillArgs &a, hipStream_t st) {
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
   const uint32_t block = SMALL ? a.c.n / 4 : kBlock;
-  hipLaunchKernelGGL(kern, dim3(a.nitems), dim3(block), lds, st, a);
+  const uint32_t per = a.items_per_wg ? a.items_per_wg : 1;
+  hipLaunchKernelGGL(kern, dim3((a.nitems + per - 1) / per), dim3(block), lds, st, a);
   return hipGetLastError();
 }
 

@@ -179,10 +179,26 @@ def test_tuning_variants_bit_exact(db, nt, oc, n, out):
     assert_bits_equal(g, o, "work list")
 
 
+@pytest.mark.parametrize("spw", [2, 3, 4, 16])
+@pytest.mark.parametrize("n,db", [(4096, 1), (4096, 0), (1024, 1), (256, 0)])
+def test_streams_per_workgroup_bit_exact(spw, n, db):
+    ns = 7  # not a multiple of spw: the last workgroup runs fewer streams
+    p = Pair(ns, pool_n=n, R=2, seed=41)
+    p.gpu.set_tuning(streams_per_wg=spw, lds_double_buffer=db)
+    assert p.gpu.tuning().streams_per_wg == spw
+    g, o = p.fill(np.arange(ns), [3 * (n - 1) + 11] * ns)
+    assert_bits_equal(g, o, "all streams")
+    g, o = p.fill(np.arange(2, ns), [n + 3] * (ns - 2), W.WN_BF16)
+    assert_bits_equal(g, o, "streams 2..6")
+    g, o = p.fill(np.arange(ns), [0] * ns)
+    assert g.size == 0
+
+
 def test_tuning_rejects_bad_values():
     g = W.Generator(2, pool_n=64, R=1)
     for field, value in (("lds_double_buffer", 2), ("long_priority_pct", 101),
-                         ("waves_per_simd", 7), ("wgs_per_cu", 17)):
+                         ("waves_per_simd", 7), ("wgs_per_cu", 17), ("streams_per_wg", 0),
+                         ("streams_per_wg", 17)):
         t = g.tuning()
         setattr(t, field, value)
         with pytest.raises(W.WnError) as ei:

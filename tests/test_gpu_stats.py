@@ -123,6 +123,17 @@ def test_stats_do_not_depend_on_launch_form():
     assert res[0] == res[1]
 
 
+def test_stats_do_not_depend_on_streams_per_workgroup():
+    res = []
+    for spw in (1, 4, 5):
+        g = W.Generator(9, pool_n=4096, R=2)
+        g.seed(6)
+        g.set_tuning(streams_per_wg=spw)
+        _, st = run(g, np.arange(9), [5 * 4095 + 7] * 9)
+        res.append(bytes(st))
+    assert res[0] == res[1] == res[2]
+
+
 def test_stats_reject_bad_arguments():
     import torch
     g = W.Generator(2, pool_n=64, R=1)
