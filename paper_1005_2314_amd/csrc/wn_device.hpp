@@ -264,13 +264,12 @@ struct Cast<Half> {
 };
 
 // ---- fused statistics -----------------------------------------------------------------
-// The emitted value as the caller receives it, widened to binary64.
-__device__ __forceinline__ double widen(float v) { return double(v); }
+// The emitted value as the statistics see it: binary32 for the binary32 and
+// 16-bit outputs (every such value is exact in binary32), binary64 for binary64.
+__device__ __forceinline__ float widen(float v) { return v; }
 __device__ __forceinline__ double widen(double v) { return v; }
-__device__ __forceinline__ double widen(Bf16 v) { return double(__uint_as_float(uint32_t(v.u) << 16)); }
-__device__ __forceinline__ double widen(Half v) {
-  return double(float(__builtin_bit_cast(_Float16, v.u)));
-}
+__device__ __forceinline__ float widen(Bf16 v) { return __uint_as_float(uint32_t(v.u) << 16); }
+__device__ __forceinline__ float widen(Half v) { return float(__builtin_bit_cast(_Float16, v.u)); }
 
 constexpr uint32_t kHistSlots = kHistBins + 2;  // bins, then below -8 and at or above 8
 // statistics LDS: 16 partial-sum slots, 4 per-wave flag words, the histogram
@@ -279,26 +278,40 @@ constexpr size_t kStatsLds =
 static_assert(((kHistSlots * 4 + 15) / 16) * 16 - kHistSlots * 4 >= 8,
               "the histogram's padding holds the persistent kernel's item word");
 
-// Per-thread sums of y .. y^4 in emission order, and the workgroup's LDS
-// histogram: bin floor(256 y) + 2048 for y in [-8, 8) (256 y is exact).
+// Per-thread binary64 sums of y .. y^4 in emission order, and the
+// workgroup's LDS histogram: bin floor(256 y) + 2048 for y in [-8, 8).  The
+// square y2 is rounded once (exact for a binary32 y); y^3 and y^4 enter their
+// sums through one fused multiply-add each.  The bin is taken in the value's
+// own type, where 256 y is exact.
 struct StatsAcc {
   double m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
   uint32_t *hist = nullptr;
-  __device__ __forceinline__ void add(double y) {
+  __device__ __forceinline__ void moments(double y) {
     const double y2 = __dmul_rn(y, y);
     m1 = __dadd_rn(m1, y);
     m2 = __dadd_rn(m2, y2);
-    m3 = __dadd_rn(m3, __dmul_rn(y2, y));
-    m4 = __dadd_rn(m4, __dmul_rn(y2, y2));
-    const double z = __dmul_rn(y, 256.0);
+    m3 = __fma_rn(y2, y, m3);
+    m4 = __fma_rn(y2, y2, m4);
+  }
+  template <typename V>
+  __device__ __forceinline__ void bin(V y) {
+    const V z = y * V(256);
     uint32_t slot;
-    if (!(z >= -2048.0))
+    if (!(z >= V(-2048)))
       slot = kHistBins;
-    else if (z >= 2048.0)
+    else if (z >= V(2048))
       slot = kHistBins + 1;
     else
       slot = uint32_t(int32_t(floor(z)) + 2048);
     atomicAdd(hist + slot, 1u);
+  }
+  __device__ __forceinline__ void add(float y) {
+    moments(double(y));
+    bin(y);
+  }
+  __device__ __forceinline__ void add(double y) {
+    moments(y);
+    bin(y);
   }
 };
 
