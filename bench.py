@@ -36,7 +36,8 @@ def parse():
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_fill_batched_f32_hbm_traffic.md")
 FILL_SOURCES = [os.path.join(ROOT, "paper_1005_2314_amd", "csrc", f)
-                for f in ("wn_device.hpp", "wn_launch_f32.hip", "wn_internal.hpp")]
+                for f in ("wn_device.hpp", "wn_launch.hpp", "wn_launch_f32_f32.hip",
+                          "wn_internal.hpp")]
 
 
 def measured_traffic():

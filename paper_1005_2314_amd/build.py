@@ -12,11 +12,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwn.so")
+# one launch unit per (pool type, output type), compiled in parallel
+LAUNCH_UNITS = ("wn_launch_f32_f32.hip", "wn_launch_f32_bf16.hip", "wn_launch_f32_f16.hip",
+                "wn_launch_f64_f64.hip", "wn_launch_f64_f32.hip", "wn_launch_f64_bf16.hip",
+                "wn_launch_f64_f16.hip")
 SOURCES = [os.path.join(CSRC, f) for f in
-           ("wn_launch_f32.hip", "wn_launch_f64.hip", "wn_stats.hip", "wn_bench.hip",
-            "wn_api.cpp")]
-HEADERS = [os.path.join(CSRC, "wn_internal.hpp"), os.path.join(CSRC, "wn_device.hpp"),
-           os.path.join(ROOT, "include", "wn.h"), os.path.join(ROOT, "include", "wn_bench.h")]
+           LAUNCH_UNITS + ("wn_stats.hip", "wn_bench.hip", "wn_api.cpp")]
+HEADERS = [os.path.join(CSRC, f) for f in ("wn_internal.hpp", "wn_device.hpp", "wn_launch.hpp")] + [
+    os.path.join(ROOT, "include", "wn.h"), os.path.join(ROOT, "include", "wn_bench.h")]
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,6 +1,6 @@
 // gfx950 device code of the Wallace maximum-entropy normal generator
-// (included by the per-pool-type launch units wn_launch_f32.hip and
-// wn_launch_f64.hip)
+// (included by the launch units wn_launch_<pool>_<out>.hip through
+// wn_launch.hpp, and by wn_stats.hip)
 // (R. P. Brent, "Some Comments on C. S. Wallace's Random Number Generators",
 // Section 5).
 //
@@ -993,7 +993,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_persistent(FillArgs a) {
   }
 }
 
-__global__ void k_reset_counter(uint32_t *ctr) {
+[[maybe_unused]] __global__ void k_reset_counter(uint32_t *ctr) {
   if (threadIdx.x == 0) *ctr = 0u;
 }
 

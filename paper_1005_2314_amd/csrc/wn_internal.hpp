@@ -121,31 +121,63 @@ hipError_t zero_words(void *p, uint32_t nwords, hipStream_t s);  // a kernel, no
 hipError_t stats_reduce(const StatsPartial *partials, uint32_t nreq, StatsOut *out,
                         hipStream_t s);
 
-// Launchers, one translation unit per pool type (wn_launch_f32.hip,
-// wn_launch_f64.hip).  Return hipSuccess or the launch error.
-hipError_t f32_seed(const SeedArgs &a, hipStream_t s);
-hipError_t f64_seed(const SeedArgs &a, hipStream_t s);
-hipError_t f32_fill(const FillArgs &a, uint32_t out_dtype, hipStream_t s);
-hipError_t f64_fill(const FillArgs &a, uint32_t out_dtype, hipStream_t s);
-// Persistent launch over items of pool sizes 1024..max_n (mixed), `grid`
-// workgroups (0 = as many as can be resident); resets a.counter first (a
-// kernel, not a memset, so that the two launches can be captured in a graph).
-hipError_t f32_fill_persistent(const FillArgs &a, uint32_t out_dtype, uint32_t max_n,
-                               uint32_t grid, hipStream_t s);
-hipError_t f64_fill_persistent(const FillArgs &a, uint32_t out_dtype, uint32_t max_n,
-                               uint32_t grid, hipStream_t s);
+// Launchers, one translation unit per pool type and output type
+// (wn_launch_<pool>_<out>.hip, instances of wn_launch.hpp).  Return hipSuccess
+// or the launch error.  The persistent launchers run items of pool sizes
+// 1024..max_n (mixed) on `grid` workgroups (0 = as many as can be resident).
+hipError_t seed_f32(const SeedArgs &a, hipStream_t s);
+hipError_t seed_f64(const SeedArgs &a, hipStream_t s);
+#define WN_DECLARE_LAUNCH_UNIT(P, Q)                                              \
+  hipError_t fill_##P##_##Q(const FillArgs &a, hipStream_t s);                   \
+  hipError_t persistent_##P##_##Q(const FillArgs &a, uint32_t max_n, uint32_t grid, \
+                                  hipStream_t s);
+WN_DECLARE_LAUNCH_UNIT(f32, f32)
+WN_DECLARE_LAUNCH_UNIT(f32, bf16)
+WN_DECLARE_LAUNCH_UNIT(f32, f16)
+WN_DECLARE_LAUNCH_UNIT(f64, f64)
+WN_DECLARE_LAUNCH_UNIT(f64, f32)
+WN_DECLARE_LAUNCH_UNIT(f64, bf16)
+WN_DECLARE_LAUNCH_UNIT(f64, f16)
+#undef WN_DECLARE_LAUNCH_UNIT
 
 inline hipError_t launch_seed(const SeedArgs &a, bool pool_f64, hipStream_t s) {
-  return pool_f64 ? f64_seed(a, s) : f32_seed(a, s);
+  return pool_f64 ? seed_f64(a, s) : seed_f32(a, s);
 }
 inline hipError_t launch_fill(const FillArgs &a, bool pool_f64, uint32_t out_dtype,
                               hipStream_t s) {
-  return pool_f64 ? f64_fill(a, out_dtype, s) : f32_fill(a, out_dtype, s);
+  if (pool_f64) {
+    switch (out_dtype) {
+      case kOutF64: return fill_f64_f64(a, s);
+      case kOutF32: return fill_f64_f32(a, s);
+      case kOutBF16: return fill_f64_bf16(a, s);
+      case kOutF16: return fill_f64_f16(a, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (out_dtype) {
+    case kOutF32: return fill_f32_f32(a, s);
+    case kOutBF16: return fill_f32_bf16(a, s);
+    case kOutF16: return fill_f32_f16(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 inline hipError_t launch_fill_persistent(const FillArgs &a, bool pool_f64, uint32_t out_dtype,
                                          uint32_t max_n, uint32_t grid, hipStream_t s) {
-  return pool_f64 ? f64_fill_persistent(a, out_dtype, max_n, grid, s)
-                  : f32_fill_persistent(a, out_dtype, max_n, grid, s);
+  if (pool_f64) {
+    switch (out_dtype) {
+      case kOutF64: return persistent_f64_f64(a, max_n, grid, s);
+      case kOutF32: return persistent_f64_f32(a, max_n, grid, s);
+      case kOutBF16: return persistent_f64_bf16(a, max_n, grid, s);
+      case kOutF16: return persistent_f64_f16(a, max_n, grid, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (out_dtype) {
+    case kOutF32: return persistent_f32_f32(a, max_n, grid, s);
+    case kOutBF16: return persistent_f32_bf16(a, max_n, grid, s);
+    case kOutF16: return persistent_f32_f16(a, max_n, grid, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace wn

@@ -1,0 +1,6 @@
+// Launchers of binary32 pools with bfloat16 output:
+// instances of the templates in wn_launch.hpp.
+
+#include "wn_launch.hpp"
+
+WN_LAUNCH_UNIT(float, f32, Bf16, bf16)

@@ -1,0 +1,6 @@
+// Launchers of binary64 pools with bfloat16 output:
+// instances of the templates in wn_launch.hpp.
+
+#include "wn_launch.hpp"
+
+WN_LAUNCH_UNIT(double, f64, Bf16, bf16)
