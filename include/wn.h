@@ -70,7 +70,7 @@ typedef enum { WN_TRANSFORM_A4 = 0, WN_TRANSFORM_ROTATION = 1 } wn_transform;
 
 typedef struct {
   uint32_t struct_size;       /* sizeof(wn_config), or WN_CONFIG_V1_SIZE (fields up to device) */
-  uint32_t num_streams;       /* >= 1; stream ids are 0 .. num_streams-1 */
+  uint32_t num_streams;       /* 1 .. 2^24; stream ids are 0 .. num_streams-1 */
   const uint32_t *pool_n;     /* host array [num_streams] of pool sizes, or NULL */
   uint32_t default_pool_n;    /* pool size when pool_n == NULL */
   uint32_t passes_per_output; /* R >= 1 passes between emitted pools (Section 5.7) */
@@ -143,8 +143,9 @@ wn_status wn_seed(wn_gen *g, uint64_t seed, void *hip_stream);
  * call stopped: fill(s, a) then fill(s, b) equals fill(s, a + b) bit for bit,
  * and results never depend on batching, order or launch shape.
  * Errors: WN_EINVAL (null pointer with a non-zero count, stream id out of
- * range, a stream listed twice), WN_ESTATE (not seeded), WN_ENOTSUP (WN_F64
- * output from a binary32 pool), WN_EDEVICE (HIP failure). */
+ * range, a stream listed twice, more than 2^56 values in one call), WN_ESTATE
+ * (not seeded), WN_ENOTSUP (WN_F64 output from a binary32 pool), WN_EDEVICE
+ * (HIP failure). */
 wn_status wn_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
                   void *out, wn_dtype out_dtype, void *hip_stream);
 
@@ -227,8 +228,10 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
  * restores it (the generator must have the same configuration; it counts as
  * seeded afterwards).  Restoring a saved state and repeating the same calls
  * reproduces their outputs bit for bit.  Both are synchronous.
- * Errors: WN_EINVAL (NULL buffer, wrong size, or a state saved under another
- * configuration), WN_ESTATE (save before seed), WN_EDEVICE. */
+ * Errors: WN_EINVAL (NULL buffer, wrong size, a state saved under another
+ * configuration, or a stream header whose pool size, pool offset, cursor or
+ * flags do not fit this generator; nothing is loaded then), WN_ESTATE (save
+ * before seed), WN_EDEVICE. */
 size_t wn_state_size(const wn_gen *g);
 wn_status wn_save_state(wn_gen *g, void *host_buf, size_t bytes);
 wn_status wn_load_state(wn_gen *g, const void *host_buf, size_t bytes);

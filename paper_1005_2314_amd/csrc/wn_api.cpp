@@ -272,7 +272,10 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   if (transform > 1) return fail(WN_EINVAL, "wn_create: unknown transform %u", transform);
   if (!(std::isfinite(mean)) || !(stddev > 0.0) || !std::isfinite(stddev))
     return fail(WN_EINVAL, "wn_create: mean must be finite and stddev finite and positive");
-  if (cfg->num_streams == 0) return fail(WN_EINVAL, "wn_create: num_streams must be >= 1");
+  // one-size launches run one workgroup of up to 256 threads per stream: 2^24
+  // streams keep a grid within the 2^32 work-items of one dimension
+  if (cfg->num_streams == 0 || cfg->num_streams > (1u << 24))
+    return fail(WN_EINVAL, "wn_create: num_streams must be in [1, 2^24]");
   if (cfg->passes_per_output == 0 || cfg->passes_per_output > 64)
     return fail(WN_EINVAL, "wn_create: passes_per_output must be in [1, 64]");
   if (cfg->pool_dtype != WN_F32 && cfg->pool_dtype != WN_F64)
@@ -437,12 +440,16 @@ wn_status validate_fill(wn_gen *g, const char *who, uint32_t nreq, const uint32_
   if (!g->pool_f64 && out_dtype == WN_F64)
     return fail(WN_ENOTSUP, "%s: binary64 output needs a binary64 pool", who);
   uint64_t sum = 0;
-  bool ok = true;
+  enum { kOk, kBadId, kTwice, kTooMany } why = kOk;
   uint32_t bad = 0;
+  constexpr uint64_t kMaxTotal = uint64_t(1) << 56;  // values per call (no offset overflows)
   for (uint32_t j = 0; j < nreq; ++j) {
     const uint32_t s = streams[j];
-    if (s >= g->num_streams || g->seen[s] || counts[j] > (uint64_t(1) << 56)) {
-      ok = false;
+    why = s >= g->num_streams ? kBadId
+          : g->seen[s]        ? kTwice
+          : counts[j] > kMaxTotal - sum ? kTooMany
+                                        : kOk;
+    if (why != kOk) {
       bad = j;
       break;
     }
@@ -451,13 +458,14 @@ wn_status validate_fill(wn_gen *g, const char *who, uint32_t nreq, const uint32_
   }
   for (uint32_t j = 0; j < nreq; ++j)
     if (streams[j] < g->num_streams) g->seen[streams[j]] = 0;
-  if (!ok) {
-    if (streams[bad] >= g->num_streams)
+  switch (why) {
+    case kBadId:
       return fail(WN_EINVAL, "%s: request %u names stream %u of %u", who, bad, streams[bad],
                   g->num_streams);
-    if (counts[bad] > (uint64_t(1) << 56))
-      return fail(WN_EINVAL, "%s: request %u count too large", who, bad);
-    return fail(WN_EINVAL, "%s: stream %u listed twice", who, streams[bad]);
+    case kTwice: return fail(WN_EINVAL, "%s: stream %u listed twice", who, streams[bad]);
+    case kTooMany:
+      return fail(WN_EINVAL, "%s: request %u takes the total past 2^56 values", who, bad);
+    default: break;
   }
   if (sum > 0 && !out)
     return fail(WN_EINVAL, "%s: out is NULL with %llu values requested", who,
@@ -985,12 +993,21 @@ wn_status wn_load_state(wn_gen *g, const void *host_buf, size_t bytes) {
   const StateBlobHeader want = blob_header(g);
   if (std::memcmp(&h, &want, sizeof(h)) != 0)
     return fail(WN_EINVAL, "wn_load_state: the state was saved under another configuration");
+  const auto *src = static_cast<const unsigned char *>(host_buf);
+  // Every saved header must describe this generator's own pool (size and
+  // arena offset) with a cursor inside it: the kernels size and index LDS
+  // and the arena from these fields.
+  for (uint32_t s = 0; s < g->num_streams; ++s) {
+    wn::StreamHdr hs;
+    std::memcpy(&hs, src + sizeof(h) + size_t(s) * sizeof(hs), sizeof(hs));
+    if (hs.n != g->pool_n[s] || hs.pool_off != g->pool_off[s] || hs.cursor > hs.n - 1 ||
+        (hs.sflags & ~uint16_t(wn::kHeldExtreme | wn::kSeenByStats)) != 0)
+      return fail(WN_EINVAL, "wn_load_state: stream %u's saved header does not fit this "
+                             "generator (pool size, offset, cursor or flags)", s);
+  }
   hipError_t e = hipSetDevice(g->device);
   if (e == hipSuccess && g->has_last) e = hipEventSynchronize(g->last);
   if (e != hipSuccess) return hip_fail(e, "wn_load_state");
-  const auto *src = static_cast<const unsigned char *>(host_buf);
-  // pool offsets and sizes are the generator's own; the saved headers carry
-  // the same values (same configuration), so they can be copied as they are
   if ((e = hipMemcpy(g->d_hdr, src + sizeof(h), h.hdr_bytes, hipMemcpyHostToDevice)) !=
           hipSuccess ||
       (e = hipMemcpy(g->d_arena, src + sizeof(h) + h.hdr_bytes, h.arena_bytes,

@@ -60,7 +60,7 @@ def test_version1_config_accepted_and_v2_fields_validated():
 
 
 @pytest.mark.parametrize("kw", [
-    dict(num_streams=0), dict(pool_n=1000), dict(pool_n=8), dict(pool_n=32768),
+    dict(num_streams=0), dict(num_streams=(1 << 24) + 1), dict(pool_n=1000), dict(pool_n=8), dict(pool_n=32768),
     dict(R=0), dict(R=65), dict(pool_dtype=W.WN_BF16), dict(chi2=7),
     dict(pool_n=[1024, 3000])])
 def test_bad_config_is_einval(kw):

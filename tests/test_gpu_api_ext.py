@@ -104,3 +104,44 @@ def test_library_first_then_torch_in_a_fresh_process():
                        timeout=240)
     assert r.returncode == 0, r.stderr[-2000:]
     assert "ok 3000 True" in r.stdout
+
+
+def test_request_validation_messages_and_total_cap():
+    g = W.Generator(3, pool_n=64, R=1)
+    g.seed(1)
+    dummy = W.C.c_void_p(16)  # never dereferenced: every request below is refused first
+    cases = [([0, 3], [5, 5], "names stream 3"), ([1, 1], [5, 5], "listed twice"),
+             ([0, 1], [1 << 56, 1], "past 2^56")]
+    for streams, counts, text in cases:
+        with pytest.raises(W.WnError) as ei:
+            W.wn_fill(g._h, streams, counts, dummy, W.WN_F32)
+        assert ei.value.status == W.WN_EINVAL and text in str(ei.value), (streams, str(ei.value))
+    # the refused requests changed nothing
+    a = g.fill([0, 1, 2], [200, 200, 200])
+    ref = W.Generator(3, pool_n=64, R=1)
+    ref.seed(1)
+    b = ref.fill([0, 1, 2], [200, 200, 200])
+    np.testing.assert_array_equal(to_numpy_bits(a), to_numpy_bits(b))
+
+
+def test_load_state_rejects_headers_that_do_not_fit():
+    """A state blob is a 72-byte configuration header, then one 64-byte header
+    per stream (pool size at byte 48, cursor at 52, flags at 54), then the
+    pools.  Headers that disagree with the generator's own pools are refused
+    and nothing is loaded."""
+    import struct
+    g = W.Generator(3, pool_n=1024, R=2)
+    g.seed(2)
+    g.fill([0, 1, 2], [700, 1500, 3])
+    blob = bytearray(g.save_state())
+    expect = to_numpy_bits(g.fill([0, 1, 2], [300, 300, 300]))
+    g.load_state(bytes(blob))
+    for stream, offset, fmt, value in ((1, 48, "<I", 2048), (0, 52, "<H", 1024),
+                                       (2, 52, "<H", 60000), (1, 54, "<H", 8), (0, 40, "<Q", 1 << 40)):
+        bad = bytearray(blob)
+        struct.pack_into(fmt, bad, 72 + 64 * stream + offset, value)
+        with pytest.raises(W.WnError) as ei:
+            g.load_state(bytes(bad))
+        assert ei.value.status == W.WN_EINVAL, (stream, offset)
+    # the refusals left the restored state in place
+    np.testing.assert_array_equal(to_numpy_bits(g.fill([0, 1, 2], [300, 300, 300])), expect)
