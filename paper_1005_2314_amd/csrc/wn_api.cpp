@@ -210,11 +210,6 @@ hipError_t record_last(wn_gen *g, hipStream_t st) {
   return e;
 }
 
-bool alloc_fault_injected() {
-  const char *v = std::getenv("WN_FAULT_ALLOC");
-  return v && v[0] == '1';
-}
-
 }  // namespace
 
 namespace {
@@ -344,10 +339,6 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   }
 
   hipError_t e = hipSuccess;
-  if (alloc_fault_injected()) {
-    delete g;
-    return fail(WN_ENOMEM, "wn_create: device allocation failed (injected)");
-  }
   if ((e = hipMalloc(&g->d_arena, g->arena_bytes)) != hipSuccess ||
       (e = hipMalloc(&g->d_hdr, sizeof(wn::StreamHdr) * g->num_streams)) != hipSuccess ||
       (e = hipMalloc(&g->d_err, sizeof(uint32_t))) != hipSuccess) {
