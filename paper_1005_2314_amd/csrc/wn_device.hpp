@@ -813,9 +813,19 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   }
 
   const double nd = double(n);
+  // k mod K, kept as a counter (one 64-bit division per work item, not per pool)
+  const uint32_t K = a.c.K;
+  uint32_t k_mod = K ? uint32_t(k % K) : 0u;
+  const bool rescale = a.c.chi2 != kChi2Off;
   while (count > 0) {
-    const bool renorm = k > 0 && a.c.K > 0 && (k % a.c.K) == 0;
-    const double g = renorm ? __dsqrt_rn(__ddiv_rn(nd, qlast)) : 1.0;
+    const bool renorm = k > 0 && K > 0 && k_mod == 0;
+    double g = 1.0;
+    if (renorm) g = __dsqrt_rn(__ddiv_rn(nd, qlast));
+    // with the previous pool's withheld value as the source (the default), the
+    // chi-square sample does not depend on this pool: take it off the chain
+    // that follows the sum of squares
+    double S = 0.0;
+    if (rescale && !x_current) S = chi2_sample(cc, a.c.chi2, xnext);
     for (uint32_t r = 0; r < a.c.R; ++r) {
       const uint64_t u1 = xs_next(xs);
       const uint64_t u2 = xs_next(xs);
@@ -825,10 +835,9 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     const double Q = e.sumsq();
     const double last = double(e.last());
     double fk = 1.0;
-    if (a.c.chi2 != kChi2Off) {
-      double x_src = xnext;
-      if (x_current) x_src = last;
-      fk = __dsqrt_rn(__ddiv_rn(chi2_sample(cc, a.c.chi2, x_src), Q));
+    if (rescale) {
+      if (x_current) S = chi2_sample(cc, a.c.chi2, last);
+      fk = __dsqrt_rn(__ddiv_rn(S, Q));
     }
     if (e.tid == 0) flag_fault(a.c.err, Q);
     f = fk;
@@ -858,6 +867,7 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
       prev_seen = true;
     }
     k += 1;
+    if (K) k_mod = k_mod + 1 == K ? 0u : k_mod + 1;
     const uint32_t take = take_of(count, n - 1);
     const T fT = scale_of(f);
     if (has_mu)
