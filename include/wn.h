@@ -69,7 +69,8 @@ typedef enum { WN_X_PREVIOUS = 0, WN_X_CURRENT = 1 } wn_chi2_source;
 typedef enum { WN_TRANSFORM_A4 = 0, WN_TRANSFORM_ROTATION = 1 } wn_transform;
 
 typedef struct {
-  uint32_t struct_size;       /* sizeof(wn_config), or WN_CONFIG_V1_SIZE (fields up to device) */
+  uint32_t struct_size;       /* sizeof(wn_config), or WN_CONFIG_V1_SIZE (fields up to device)
+                                 or WN_CONFIG_V2_SIZE (fields up to stddev) */
   uint32_t num_streams;       /* 1 .. 2^24; stream ids are 0 .. num_streams-1 */
   const uint32_t *pool_n;     /* host array [num_streams] of pool sizes, or NULL */
   uint32_t default_pool_n;    /* pool size when pool_n == NULL */
@@ -83,11 +84,19 @@ typedef struct {
   wn_transform transform;     /* default WN_TRANSFORM_A4 */
   double mean;                /* mu added to every output (0: none) */
   double stddev;              /* sigma > 0 folded into the scale (1: none) */
+  /* version 3 */
+  uint32_t emit_stride;       /* t in 1..16 (0 means 1): each stream returns every t-th value
+                                 of its underlying sequence, starting with the first; the
+                                 "use every third value" option of Section 5.7.  Pool
+                                 statistics describe the underlying pools. */
+  uint32_t reserved;          /* 0 */
 } wn_config;
 #define WN_CONFIG_V1_SIZE 40u
+#define WN_CONFIG_V2_SIZE 64u
 /* Pool sizes are powers of two in [16, 16384].  The library copies the
- * configuration (and pool_n) during wn_create.  A version-1 struct (size
- * WN_CONFIG_V1_SIZE) gets the version-2 defaults.  With mean mu and stddev
+ * configuration (and pool_n) during wn_create.  A shorter struct (size
+ * WN_CONFIG_V1_SIZE or WN_CONFIG_V2_SIZE) gets the defaults of the fields it
+ * lacks.  With mean mu and stddev
  * sigma, value i of pool k is T(P[i] * T(f_k * sigma)), plus T(mu) in the pool
  * type when mu != 0 (Section 5.5: sigma costs nothing, being folded into the
  * scale); sigma = 1, mu = 0 leave the generator's bits unchanged. */

@@ -20,7 +20,8 @@ _OUT_NP = {F64: np.float64, F32: np.float32, BF16: np.uint16, F16: np.uint16}
 class _Config(C.Structure):
     _fields_ = [(name, C.c_uint32) for name in (
         "num_streams", "default_pool_n", "R", "pool_f64", "chi2", "K", "hazard", "warmup",
-        "trace", "x_current", "transform", "pad")] + [("mean", C.c_double), ("stddev", C.c_double)]
+        "trace", "x_current", "transform", "emit_stride")] + [("mean", C.c_double),
+                                                              ("stddev", C.c_double)]
 
 
 class StreamInfo(C.Structure):
@@ -214,7 +215,7 @@ class Generator:
 
     def __init__(self, num_streams, pool_n=4096, R=2, pool_dtype="f32", chi2=CHI2_CUBIC,
                  K=16, hazard=HAZ_NONE, warmup=0, trace=False, x_current=False, transform=0,
-                 mean=0.0, stddev=1.0):
+                 mean=0.0, stddev=1.0, emit_stride=1):
         self.num_streams = int(num_streams)
         per_stream = None
         if np.ndim(pool_n) > 0:
@@ -225,7 +226,8 @@ class Generator:
             default = int(pool_n)
         self.pool_f64 = pool_dtype in ("f64", "float64", np.float64)
         cfg = _Config(self.num_streams, default, R, int(self.pool_f64), chi2, K, hazard, warmup,
-                      int(bool(trace)), int(bool(x_current)), transform, 0, mean, stddev)
+                      int(bool(trace)), int(bool(x_current)), transform, emit_stride, mean,
+                      stddev)
         self._pool_n = per_stream
         self._h = lib().orc_create(C.byref(cfg),
                                    per_stream.ctypes.data if per_stream is not None else None)

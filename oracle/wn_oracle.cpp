@@ -429,6 +429,7 @@ struct Config {
   uint32_t transform;  // 0: the 4x4 family; 1: plane rotations
   double mean;         // added to every output when non-zero
   double stddev;       // folded into the scale
+  uint32_t stride;     // the stream returns every stride-th underlying value
 };
 
 inline uint32_t ilog2(uint32_t v) {
@@ -533,6 +534,28 @@ struct Gen {
     if (!st.ready) init_stream(s);
     const Chi2Consts cc = chi2_consts(st.n);
     const T muT = T(cfg.mean);
+    if (cfg.stride > 1) {
+      // Section 5.7's "every third value", for any stride t: the stream is
+      // every t-th value of the underlying sequence (the n-1 emitted positions
+      // of pool 0, then of pool 1, ...), starting with the first.  Position j
+      // of the current pool (index k-1) is underlying value (k-1)(n-1) + j.
+      while (count > 0) {
+        if (st.cursor == st.n - 1) produce_pool(st, cc);
+        const T fT = T(st.f * cfg.stddev);
+        const uint64_t first = (st.k - 1) * uint64_t(st.n - 1);
+        while (st.cursor < st.n - 1 && count > 0) {
+          if ((first + st.cursor) % cfg.stride == 0) {
+            T y = st.P[st.cursor] * fT;
+            if (cfg.mean != 0.0) y = y + muT;
+            store_out(out, off, y, dtype);
+            ++off;
+            --count;
+          }
+          ++st.cursor;
+        }
+      }
+      return;
+    }
     while (count > 0) {
       if (st.cursor == st.n - 1) produce_pool(st, cc);
       const T fT = T(st.f * cfg.stddev);
@@ -574,7 +597,7 @@ struct orc_config {
   uint32_t trace;
   uint32_t x_current;
   uint32_t transform;
-  uint32_t pad;
+  uint32_t emit_stride;  // 0 or 1: every value; t: every t-th value
   double mean;
   double stddev;
 };
@@ -703,9 +726,10 @@ void *orc_create(const orc_config *cfg, const uint32_t *pool_n) {
   if (!cfg || cfg->num_streams == 0 || cfg->R == 0) return nullptr;
   auto *g = new OrcGen();
   g->pool_f64 = cfg->pool_f64;
-  if (!(cfg->stddev > 0.0) || cfg->transform > 1) return nullptr;
+  if (!(cfg->stddev > 0.0) || cfg->transform > 1 || cfg->emit_stride > 16) return nullptr;
   Config c{cfg->num_streams, cfg->R,         cfg->chi2,      cfg->K,    cfg->hazard, cfg->warmup,
-           cfg->trace,       cfg->x_current, cfg->transform, cfg->mean, cfg->stddev};
+           cfg->trace,       cfg->x_current, cfg->transform, cfg->mean, cfg->stddev,
+           cfg->emit_stride ? cfg->emit_stride : 1u};
   std::vector<uint32_t> ns(cfg->num_streams);
   for (uint32_t s = 0; s < cfg->num_streams; ++s) {
     ns[s] = pool_n ? pool_n[s] : cfg->default_pool_n;

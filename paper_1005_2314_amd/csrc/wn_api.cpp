@@ -113,7 +113,7 @@ struct wn_gen {
   int device = 0;
   uint32_t num_streams = 0;
   uint32_t R = 1, K = 0, chi2 = 0;
-  uint32_t x_current = 0, transform = 0;
+  uint32_t x_current = 0, transform = 0, stride = 1;
   double mean = 0.0, stddev = 1.0;
   bool pool_f64 = false;
   std::vector<uint32_t> pool_n;     // per stream
@@ -162,6 +162,7 @@ wn::KernelCommon common(const wn_gen *g, uint32_t n) {
   c.has_mu = g->mean != 0.0;
   c.transform = g->transform;
   c.unit_sigma = g->stddev == 1.0 ? 1u : 0u;
+  c.stride = g->stride;
   c.sigma = g->stddev;
   c.mu = g->mean;
   for (int i = 0; i < wn::kNumSizes; ++i) {
@@ -215,7 +216,7 @@ hipError_t record_last(wn_gen *g, hipStream_t st) {
 namespace {
 struct StateBlobHeader {  // prefix of a saved state
   uint64_t magic;         // "WNSTATE1"
-  uint32_t num_streams, pool_f64, R, K, chi2, x_current, transform, pad;
+  uint32_t num_streams, pool_f64, R, K, chi2, x_current, transform, stride;
   double mean, stddev;
   uint64_t arena_bytes, hdr_bytes;
 };
@@ -231,6 +232,7 @@ StateBlobHeader blob_header(const wn_gen *g) {
   h.chi2 = g->chi2;
   h.x_current = g->x_current;
   h.transform = g->transform;
+  h.stride = g->stride;
   h.mean = g->mean;
   h.stddev = g->stddev;
   h.arena_bytes = g->arena_bytes;
@@ -254,11 +256,16 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   if (!out_gen) return fail(WN_EINVAL, "wn_create: out_gen is NULL");
   *out_gen = nullptr;
   if (!cfg) return fail(WN_EINVAL, "wn_create: cfg is NULL");
-  if (cfg->struct_size != sizeof(wn_config) && cfg->struct_size != WN_CONFIG_V1_SIZE)
-    return fail(WN_EINVAL, "wn_create: struct_size %u, expected %zu or %u", cfg->struct_size,
-                sizeof(wn_config), WN_CONFIG_V1_SIZE);
+  if (cfg->struct_size != sizeof(wn_config) && cfg->struct_size != WN_CONFIG_V1_SIZE &&
+      cfg->struct_size != WN_CONFIG_V2_SIZE)
+    return fail(WN_EINVAL, "wn_create: struct_size %u, expected %zu, %u or %u", cfg->struct_size,
+                sizeof(wn_config), WN_CONFIG_V2_SIZE, WN_CONFIG_V1_SIZE);
   static_assert(offsetof(wn_config, chi2_source) == WN_CONFIG_V1_SIZE, "v1 prefix");
-  const bool v2 = cfg->struct_size == sizeof(wn_config);
+  static_assert(offsetof(wn_config, emit_stride) == WN_CONFIG_V2_SIZE, "v2 prefix");
+  const bool v2 = cfg->struct_size >= WN_CONFIG_V2_SIZE;
+  const bool v3 = cfg->struct_size == sizeof(wn_config);
+  const uint32_t stride = v3 && cfg->emit_stride ? cfg->emit_stride : 1u;
+  if (stride > 16) return fail(WN_EINVAL, "wn_create: emit_stride %u, at most 16", stride);
   const uint32_t x_src = v2 ? uint32_t(cfg->chi2_source) : 0u;
   const uint32_t transform = v2 ? uint32_t(cfg->transform) : 0u;
   const double mean = v2 ? cfg->mean : 0.0;
@@ -304,6 +311,7 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   g->chi2 = uint32_t(cfg->chi2);
   g->x_current = x_src;
   g->transform = transform;
+  g->stride = stride;
   g->mean = mean;
   g->stddev = stddev;
   g->pool_f64 = cfg->pool_dtype == WN_F64;
@@ -619,7 +627,7 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
     for (uint32_t j = 0; j < nreq; ++j) {
       const uint32_t n = g->pool_n[streams[j]];
       if (counts[j] == 0 || n < 1024) continue;
-      const uint64_t pools = counts[j] / (n - 1) + 1;
+      const uint64_t pools = counts[j] * g->stride / (n - 1) + 1;
       order.emplace_back(pools * n, j);
     }
     std::stable_sort(order.begin(), order.end(),

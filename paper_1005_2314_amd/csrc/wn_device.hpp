@@ -620,6 +620,28 @@ struct Engine {
         }
       }
   }
+
+  // Thinned emission: positions j0, j0 + t, ..., j0 + (take-1) t go to
+  // out[obase], out[obase + 1], ... (every t-th value of the stream).
+  template <bool NT, bool STATS, typename O>
+  __device__ __forceinline__ void emit_thin(O *__restrict__ out, uint64_t obase, uint32_t j0,
+                                            uint32_t t, uint32_t take, T fT, StatsAcc *sa,
+                                            bool has_mu, T muT) const {
+    const uint32_t span = (take - 1) * t;  // last position - j0
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) {
+        const uint32_t i = pos(m, c);
+        const uint32_t d = i - j0;  // wraps past span when i < j0
+        if (i >= j0 && d <= span && d % t == 0) {
+          const O v = Cast<O>::from(has_mu ? scaled<true>(y[c][m], fT, muT)
+                                           : scaled<false>(y[c][m], fT, muT));
+          put<NT>(out + (obase + d / t), v);
+          if constexpr (STATS) sa->add(widen(v));
+        }
+      }
+  }
 };
 
 template <typename T, int NQ, bool SMALL, bool DB>
@@ -800,16 +822,46 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   const bool x_current = __builtin_amdgcn_readfirstlane(a.c.x_current) != 0;
   const T muT = T(a.c.mu);
   auto scale_of = [&](double fk) -> T { return unit_sigma ? T(fk) : T(__dmul_rn(fk, a.c.sigma)); };
+  // Thinning (stride t > 1): the stream is every t-th value of the underlying
+  // sequence, position j of pool q being underlying value q (n-1) + j.  ph is
+  // the current pool's phase (q (n-1)) mod t, ph_next the next pool's.
+  const uint32_t t = __builtin_amdgcn_readfirstlane(a.c.stride);
+  uint32_t ph = 0, ph_next = 0;
+  if (t > 1) {
+    const uint32_t step = (n - 1) % t;
+    ph_next = uint32_t((k % t) * step % t);
+    ph = (ph_next + t - step) % t;
+  }
+  // emit up to `count` of this pool's values from `cursor` in thinned order;
+  // returns how many, and moves the cursor past the last one emitted
+  auto emit_thinned = [&](uint32_t &cur, const T fT) -> uint32_t {
+    const uint32_t r = (ph + cur) % t;
+    const uint32_t j0 = cur + (r ? t - r : 0u);
+    const uint32_t avail = j0 < n - 1 ? (n - 2 - j0) / t + 1 : 0u;
+    const uint32_t take = take_of(count, avail);
+    if (take == 0) {
+      cur = n - 1;
+      return 0u;
+    }
+    e.template emit_thin<NT, STATS>(out, obase, j0, t, take, fT, &sa, has_mu, muT);
+    cur = j0 + (take - 1) * t + 1;
+    return take;
+  };
   if (cursor < n - 1) {
-    const uint32_t take = take_of(count, n - 1 - cursor);
     const T fT = scale_of(f);
-    if (has_mu)
-      e.template emit<NT, STATS, true>(out, obase, cursor, cursor + take, fT, &sa, muT);
-    else
-      e.template emit<NT, STATS, false>(out, obase, cursor, cursor + take, fT, &sa, muT);
+    uint32_t take;
+    if (t > 1) {
+      take = emit_thinned(cursor, fT);
+    } else {
+      take = take_of(count, n - 1 - cursor);
+      if (has_mu)
+        e.template emit<NT, STATS, true>(out, obase, cursor, cursor + take, fT, &sa, muT);
+      else
+        e.template emit<NT, STATS, false>(out, obase, cursor, cursor + take, fT, &sa, muT);
+      cursor += take;
+    }
     obase += take;
     count -= take;
-    cursor += take;
   }
 
   const double nd = double(n);
@@ -868,15 +920,23 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     }
     k += 1;
     if (K) k_mod = k_mod + 1 == K ? 0u : k_mod + 1;
-    const uint32_t take = take_of(count, n - 1);
     const T fT = scale_of(f);
-    if (has_mu)
-      e.template emit<NT, STATS, true>(out, obase, 0, take, fT, &sa, muT);
-    else
-      e.template emit<NT, STATS, false>(out, obase, 0, take, fT, &sa, muT);
+    uint32_t take;
+    if (t > 1) {
+      ph = ph_next;
+      ph_next = (ph_next + (n - 1) % t) % t;
+      cursor = 0;
+      take = emit_thinned(cursor, fT);
+    } else {
+      take = take_of(count, n - 1);
+      if (has_mu)
+        e.template emit<NT, STATS, true>(out, obase, 0, take, fT, &sa, muT);
+      else
+        e.template emit<NT, STATS, false>(out, obase, 0, take, fT, &sa, muT);
+      cursor = take;
+    }
     obase += take;
     count -= take;
-    cursor = take;
   }
 
   e.store_global(gpool);

@@ -29,6 +29,7 @@ EXPORTED = ("wn_create", "wn_seed", "wn_fill", "wn_sync", "wn_get_stream", "wn_d
 WN_X_PREVIOUS, WN_X_CURRENT = 0, 1
 WN_TRANSFORM_A4, WN_TRANSFORM_ROTATION = 0, 1
 WN_CONFIG_V1_SIZE = 40
+WN_CONFIG_V2_SIZE = 64
 
 
 class wn_config(C.Structure):
@@ -37,7 +38,7 @@ class wn_config(C.Structure):
                 ("passes_per_output", C.c_uint32), ("pool_dtype", C.c_int),
                 ("chi2", C.c_int), ("renorm_period", C.c_uint32), ("device", C.c_int),
                 ("chi2_source", C.c_int), ("transform", C.c_int), ("mean", C.c_double),
-                ("stddev", C.c_double)]
+                ("stddev", C.c_double), ("emit_stride", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class wn_stream_info(C.Structure):
@@ -189,7 +190,7 @@ def wn_bench_box_muller(out_ptr, count, out_dtype, seed, fast=False, stream=None
 
 def make_config(num_streams, pool_n=4096, R=2, pool_dtype=WN_F32, chi2=WN_CHI2_CUBIC, K=16,
                 device=0, chi2_source=WN_X_PREVIOUS, transform=WN_TRANSFORM_A4, mean=0.0,
-                stddev=1.0):
+                stddev=1.0, emit_stride=1):
     cfg = wn_config()
     cfg.struct_size = C.sizeof(wn_config)
     cfg.num_streams = int(num_streams)
@@ -210,6 +211,7 @@ def make_config(num_streams, pool_n=4096, R=2, pool_dtype=WN_F32, chi2=WN_CHI2_C
     cfg.transform = int(transform)
     cfg.mean = float(mean)
     cfg.stddev = float(stddev)
+    cfg.emit_stride = int(emit_stride)
     return cfg, keep
 
 
@@ -232,9 +234,9 @@ class Generator:
 
     def __init__(self, num_streams, pool_n=4096, R=2, pool_dtype=WN_F32, chi2=WN_CHI2_CUBIC,
                  K=16, device=0, chi2_source=WN_X_PREVIOUS, transform=WN_TRANSFORM_A4,
-                 mean=0.0, stddev=1.0):
+                 mean=0.0, stddev=1.0, emit_stride=1):
         self.cfg, keep = make_config(num_streams, pool_n, R, pool_dtype, chi2, K, device,
-                                     chi2_source, transform, mean, stddev)
+                                     chi2_source, transform, mean, stddev, emit_stride)
         self.num_streams = int(num_streams)
         self.pool_f64 = pool_dtype == WN_F64
         self.device = device

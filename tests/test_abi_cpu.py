@@ -33,25 +33,28 @@ def test_library_exports_every_declared_symbol():
 
 def test_config_struct_layout():
     # version 1 prefix (pointer member forces 8-byte alignment): 4+4+8+4*5+4 = 40;
-    # version 2 adds two enums and two doubles
+    # version 2 adds two enums and two doubles, version 3 the output stride
     assert W.wn_config.chi2_source.offset == W.WN_CONFIG_V1_SIZE == 40
-    assert C.sizeof(W.wn_config) == 64
+    assert W.wn_config.emit_stride.offset == W.WN_CONFIG_V2_SIZE == 64
+    assert C.sizeof(W.wn_config) == 72
     assert C.sizeof(W.wn_stream_info) == 48
     assert C.sizeof(W.wn_stats) == 8 * (1 + 4 + 2 + 1 + 2 + 1 + 1) + 8 * W.HIST_BINS + 16
     assert W.wn_stats.x_pools.offset == W.wn_stats.hist.offset + 8 * W.HIST_BINS
 
 
-def test_version1_config_accepted_and_v2_fields_validated():
+def test_older_config_versions_accepted_and_new_fields_validated():
     import torch
     if torch.cuda.is_available():
         pytest.skip("checks the validation that precedes device selection")
-    cfg, _ = W.make_config(2, 1024)
-    cfg.struct_size = W.WN_CONFIG_V1_SIZE
-    with pytest.raises(W.WnError) as ei:  # valid v1 struct: fails only for want of a device
-        W.wn_create(cfg)
-    assert ei.value.status == W.WN_EDEVICE
+    for size in (W.WN_CONFIG_V1_SIZE, W.WN_CONFIG_V2_SIZE):
+        cfg, _ = W.make_config(2, 1024)
+        cfg.struct_size = size
+        cfg.emit_stride = 99  # beyond a shorter struct: never read
+        with pytest.raises(W.WnError) as ei:  # a valid struct: fails only for want of a device
+            W.wn_create(cfg)
+        assert ei.value.status == W.WN_EDEVICE, size
     for field, value in (("stddev", 0.0), ("stddev", float("inf")), ("mean", float("nan")),
-                         ("chi2_source", 2), ("transform", 9)):
+                         ("chi2_source", 2), ("transform", 9), ("emit_stride", 17)):
         cfg, _ = W.make_config(2, 1024)
         setattr(cfg, field, value)
         with pytest.raises(W.WnError) as ei:

@@ -83,3 +83,50 @@ def test_rotations_cluster_more_than_the_4x4_family():
     r4, _ = excess(64, 1, 100000, transform=0)
     rr, _ = excess(64, 1, 100000, transform=1)
     assert rr > r4 + 0.5
+
+
+# ---- "every third value" against "the values in every third pool" (Section 5.7) --------
+
+@pytest.mark.parametrize("n,t", [(16, 2), (16, 16), (64, 3), (1024, 3), (1024, 5), (4096, 7)])
+def test_thinned_stream_is_every_t_th_value(n, t):
+    """The definition: every t-th value of the plain stream, starting with the
+    first, also across calls that end anywhere in a pool."""
+    plain = O.Generator(3, pool_n=n, R=2)
+    thin = O.Generator(3, pool_n=n, R=2, emit_stride=t)
+    plain.seed(4)
+    thin.seed(4)
+    total = 3 * (n - 1) * t + 11
+    ref = plain.fill([2], [total * t])[::t][:total]
+    parts = []
+    for c in (1, n // 3 + 2, 5, total):
+        c = min(c, total - sum(p.size for p in parts))
+        parts.append(thin.fill([2], [c]))
+    np.testing.assert_array_equal(np.concatenate(parts), ref)
+
+
+def block_clustering(y, n):
+    m = y.size // (n - 1)
+    z = np.abs(y[: m * (n - 1)].astype(np.float64)).reshape(m, n - 1).max(axis=1)
+    e = z >= O.extreme_threshold(n)
+    p = e.mean()
+    expected = (m - 1) * p * p
+    return np.count_nonzero(e[1:] & e[:-1]) / expected
+
+
+def test_every_third_pool_beats_every_third_value():
+    """At equal cost (three underlying values per output) both options of
+    Section 5.7 weaken the adjacent-block clustering of rare values, but
+    skipping whole pools removes it while taking every third value keeps
+    part of it: n = 64, 2 x 10^5 blocks of n - 1 outputs each."""
+    n, blocks = 64, 200000
+    ratios = {}
+    for label, kw in (("plain", dict(R=1)), ("pools", dict(R=3)),
+                      ("values", dict(R=1, emit_stride=3))):
+        g = O.Generator(4, pool_n=n, **kw)
+        g.seed(5)
+        per = blocks // 4 * (n - 1)
+        ratios[label] = np.mean([block_clustering(g.fill([s], [per]), n) for s in range(4)])
+    assert ratios["plain"] > 1.3
+    assert ratios["values"] > 1.05
+    assert ratios["pools"] < 1.05
+    assert ratios["pools"] < ratios["values"] < ratios["plain"]
