@@ -99,8 +99,14 @@ def cpu_baseline(w, target_seconds):
         dt = time.perf_counter() - t0
         if dt >= target_seconds:
             break
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": calls * k * per / dt, "unit": "normals/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu,
             "sample": f"streams 0..{k - 1} of {w['num_streams']} (pool 4096 f32, R=2): "
                       f"{calls} continuing calls of {per} values per stream after an untimed "
                       f"seeding call, {dt:.1f} s wall on {threads} threads"}
