@@ -87,7 +87,7 @@ typedef struct {
   /* version 3 */
   uint32_t emit_stride;       /* t in 1..16 (0 means 1): each stream returns every t-th value
                                  of its underlying sequence, starting with the first; the
-                                 "use every third value" option of Section 5.7.  Pool
+                                 option of Section 5.7 that keeps only some of the values.  Pool
                                  statistics describe the underlying pools. */
   uint32_t reserved;          /* 0 */
 } wn_config;

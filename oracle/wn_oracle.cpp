@@ -491,8 +491,8 @@ struct Gen {
   }
 
   // Produce pool k (§5.5 and §5.7): R9 renormalise every K pools using the
-  // previous pool's sum of squares; R passes (values "in every third pool"
-  // style discarding, §5.7, generalised to R passes between emitted pools);
+  // previous pool's sum of squares; R passes (§5.7's option of emitting only
+  // some pools, generalised to R passes between emitted pools);
   // sum of squares; chi-square sample from the withheld value of the previous
   // pool (the fastnorm2 choice, §5.5); scale factor f = sqrt(S / Q).
   // R10: x for the next pool is the withheld value scaled by f.  R11: the
@@ -535,7 +535,7 @@ struct Gen {
     const Chi2Consts cc = chi2_consts(st.n);
     const T muT = T(cfg.mean);
     if (cfg.stride > 1) {
-      // Section 5.7's "every third value", for any stride t: the stream is
+      // Section 5.7's option of keeping only some values, for any stride t: the stream is
       // every t-th value of the underlying sequence (the n-1 emitted positions
       // of pool 0, then of pool 1, ...), starting with the first.  Position j
       // of the current pool (index k-1) is underlying value (k-1)(n-1) + j.

@@ -79,7 +79,8 @@ def load():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+            raise ImportError(f"{LIB_PATH} is missing: build it first "
+                              "(python paper_1005_2314_amd/build.py)")
         # PyTorch ships its own HIP runtime under the same soname as the system
         # one (libamdhip64.so.7); whichever is loaded first serves the whole
         # process.  Load torch's first, so that the library runs on the runtime

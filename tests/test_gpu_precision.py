@@ -7,7 +7,7 @@ more (bf16/f16 through binary32: at most one ulp of the output type); a
 binary32 pool adds the binary32 rounding walk of the passes, bounded as in the
 oracle's own test (8 sqrt(P) 2^-24 on values of unit size, P = passes since
 seeding), plus the output rounding.  The measured errors are written to
-gpurun_out/precision.json when that folder exists.
+precision.json in the directory named by WN_REPORT_DIR, when it is set.
 """
 import json
 import math
@@ -23,7 +23,6 @@ from paper_1005_2314_amd import wn as W
 
 pytestmark = pytest.mark.gpu
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _widen(raw, oname):
@@ -84,7 +83,7 @@ def test_precision_sweep_against_binary64_oracle():
                 "sample": f"{len(sample)} streams x {per}"}
             del out
         g.close()
-    outdir = os.path.join(ROOT, "gpurun_out")
-    if os.path.isdir(outdir):
+    outdir = os.environ.get("WN_REPORT_DIR", "")
+    if outdir and os.path.isdir(outdir):
         with open(os.path.join(outdir, "precision.json"), "w") as fh:
             json.dump(report, fh, indent=1)

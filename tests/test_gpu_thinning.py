@@ -1,5 +1,5 @@
 """GPU parity of thinned streams (emit_stride t: every t-th value of the
-underlying sequence, Section 5.7's "every third value"): every pool-size
+underlying sequence, Section 5.7's option of keeping only some values): every pool-size
 class, strides that do and do not divide n - 1, pools that emit nothing
 (t > n - 1), the one-size, work-list and persistent forms, mean/stddev,
 rotations, fused statistics and the stream cursor, bit for bit against the

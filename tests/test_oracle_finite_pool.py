@@ -1,6 +1,6 @@
 """Pins of the finite-pool diagnostics (Section 5.7): rare values cluster in
-adjacent pools, and fewer emitted pools per pass ("values in every third
-pool") weaken the effect.
+adjacent pools, and emitting fewer pools per pass (only every third pool,
+say) weakens the effect.
 
 The statistic: a pool holds an extreme value when one of its n-1 emitted
 standardised values reaches c_n, the normal quantile at which about one pool
@@ -85,7 +85,7 @@ def test_rotations_cluster_more_than_the_4x4_family():
     assert rr > r4 + 0.5
 
 
-# ---- "every third value" against "the values in every third pool" (Section 5.7) --------
+# ---- keeping every third value against emitting every third pool (Section 5.7) --------
 
 @pytest.mark.parametrize("n,t", [(16, 2), (16, 16), (64, 3), (1024, 3), (1024, 5), (4096, 7)])
 def test_thinned_stream_is_every_t_th_value(n, t):
