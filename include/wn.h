@@ -131,6 +131,13 @@ typedef struct {
   uint32_t streams_per_wg;     /* one-size launches of consecutive streams with equal counts:
                                   each workgroup runs this many streams one after another
                                   (longer contiguous output runs); 1..16, default 1 */
+  uint32_t defer_emission;     /* without statistics or thinning: each pool's scale and
+                                  emission run inside the next pool's first pass, overlapping
+                                  the pass's latency (a shorter chain of pools per stream; same
+                                  results).  Bit 0: one-size launches of at most one stream per
+                                  compute unit with pools of 1024 or 2048 values; bit 1: the
+                                  items of 1024 and 2048 values of persistent launches whose
+                                  pools are at most 4096.  0..3, default 1 */
 } wn_tuning;
 
 /* Validate cfg, select the device, allocate the per-stream state in device

@@ -104,6 +104,7 @@ struct PersistentSlot {
   hipGraphExec_t exec = nullptr;
   // key of the cached graph
   uint32_t k_nitems = 0, k_dtype = 0, k_variant = 0, k_grid = 0, k_max_n = 0, k_prio = 0;
+  uint32_t k_defer = 0;
   void *k_out = nullptr;
 };
 
@@ -138,7 +139,9 @@ struct wn_gen {
   uint32_t wgs_per_cu = 0;
   uint32_t long_priority_pct = 25;
   uint32_t streams_per_wg = 1;
+  uint32_t defer_emission = 1;  // bit 0: one-size launches of few streams, bit 1: persistent
   bool use_graph = true;
+  uint32_t cus = 256;        // compute units of the device
   // persistent launches: two staging/work-list slots, each with a cached graph
   PersistentSlot pslots[2];
   unsigned next_pslot = 0;
@@ -305,6 +308,13 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   wn_gen *g = new (std::nothrow) wn_gen();
   if (!g) return fail(WN_ENOMEM, "wn_create: host allocation failed");
   g->device = cfg->device;
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device) ==
+            hipSuccess &&
+        cus > 0)
+      g->cus = uint32_t(cus);
+  }
   g->num_streams = cfg->num_streams;
   g->R = cfg->passes_per_output;
   g->K = cfg->renorm_period;
@@ -506,6 +516,7 @@ hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, u
   a.variant = g->variant;
   a.counter = slot.counter;
   a.prio_items = prio_items;
+  a.defer = (g->defer_emission >> 1) & 1u;
   a.partials = stats ? g->d_partials : nullptr;
   a.stats = stats;
   int dev = 0, cus = 256;
@@ -521,7 +532,7 @@ hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, u
   }
   const bool hit = slot.exec && slot.k_nitems == nitems && slot.k_dtype == dtype &&
                    slot.k_variant == g->variant && slot.k_grid == grid && slot.k_max_n == max_n &&
-                   slot.k_out == out && slot.k_prio == prio_items;
+                   slot.k_out == out && slot.k_prio == prio_items && slot.k_defer == a.defer;
   if (!hit) {
     if (slot.exec) {
       (void)hipGraphExecDestroy(slot.exec);
@@ -550,6 +561,7 @@ hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, u
     slot.k_max_n = max_n;
     slot.k_out = out;
     slot.k_prio = prio_items;
+    slot.k_defer = a.defer;
   }
   return hipGraphLaunch(slot.exec, st);
 }
@@ -581,6 +593,9 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
     a.items_per_wg = g->streams_per_wg;
     a.out = out;
     a.variant = g->variant;
+    // few streams: each has a compute unit to itself and its chain of pools is
+    // the critical path
+    a.defer = (g->defer_emission & 1u) && nreq <= g->cus;
     a.counter = nullptr;
     a.partials = partials;
     a.stats = stats;
@@ -813,15 +828,17 @@ wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t) {
   const uint32_t wcode = w == 0 ? 0u : w == 8 ? 1u : w == 6 ? 2u : w == 5 ? 3u : 4u;
   if (t->lds_double_buffer > 1 || t->nontemporal_stores > 1 || wcode > 3 || t->use_graph > 1 ||
       (wcode && t->nontemporal_stores) || t->wgs_per_cu > 16 || t->long_priority_pct > 100 ||
-      t->streams_per_wg < 1 || t->streams_per_wg > 16)
+      t->streams_per_wg < 1 || t->streams_per_wg > 16 || t->defer_emission > 3)
     return fail(WN_EINVAL, "wn_set_tuning: flags must be 0 or 1, waves_per_simd 0/5/6/8 and "
                            "not with nontemporal_stores, wgs_per_cu <= 16, "
-                           "long_priority_pct <= 100, streams_per_wg in [1, 16]");
+                           "long_priority_pct <= 100, streams_per_wg in [1, 16], "
+                           "defer_emission <= 3");
   g->variant = t->lds_double_buffer | (t->nontemporal_stores << 1) | (wcode << 2);
   g->wgs_per_cu = t->wgs_per_cu;
   g->use_graph = t->use_graph != 0;
   g->long_priority_pct = t->long_priority_pct;
   g->streams_per_wg = t->streams_per_wg;
+  g->defer_emission = t->defer_emission;
   return WN_OK;
 }
 
@@ -836,6 +853,7 @@ wn_status wn_get_tuning(wn_gen *g, wn_tuning *t) {
   t->use_graph = g->use_graph ? 1u : 0u;
   t->long_priority_pct = g->long_priority_pct;
   t->streams_per_wg = g->streams_per_wg;
+  t->defer_emission = g->defer_emission;
   return WN_OK;
 }
 
@@ -863,8 +881,9 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
              g->pool_n[streams[j]] == g->pool_n[streams[0]];
   std::vector<wn_tuning> cands;
   auto add = [&](uint32_t db, uint32_t nt, uint32_t oc, uint32_t wpc, uint32_t prio,
-                 uint32_t spw = 1) {
+                 uint32_t spw = 1, uint32_t defer = 0) {
     wn_tuning t = cur;
+    t.defer_emission = defer;
     t.streams_per_wg = spw;
     t.lds_double_buffer = db;
     t.nontemporal_stores = nt;
@@ -873,17 +892,22 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
     t.long_priority_pct = prio;
     cands.push_back(t);
   };
+  // the deferred form is a candidate where it applies (and is otherwise ignored)
+  const uint32_t keep_defer = cur.defer_emission;
   if (affine) {
     for (uint32_t spw : {1u, 2u, 4u, 8u})
       for (uint32_t db = 0; db < 2; ++db)
         for (uint32_t wps : {0u, 5u, 6u, 8u})
-          add(db, 0, wps, cur.wgs_per_cu, cur.long_priority_pct, spw);
-    add(1, 1, 0, cur.wgs_per_cu, cur.long_priority_pct, 1);
+          add(db, 0, wps, cur.wgs_per_cu, cur.long_priority_pct, spw, keep_defer & 2u);
+    add(1, 1, 0, cur.wgs_per_cu, cur.long_priority_pct, 1, keep_defer & 2u);
+    if (nreq <= g->cus) add(1, 0, 0, cur.wgs_per_cu, cur.long_priority_pct, 1, keep_defer | 1u);
   } else {
     for (uint32_t prio : {0u, 10u, 25u})
       for (uint32_t db = 0; db < 2; ++db)
-        for (uint32_t wpc : {0u, 3u, 4u, 6u}) add(db, 0, 0, wpc, prio);
-    add(1, 1, 0, 0, 25);
+        for (uint32_t wpc : {0u, 3u, 4u, 6u}) add(db, 0, 0, wpc, prio, 1, keep_defer & 1u);
+    add(1, 1, 0, 0, 25, 1, keep_defer & 1u);
+    for (uint32_t prio : {0u, 25u})
+      for (uint32_t wpc : {0u, 2u, 3u}) add(1, 0, 0, wpc, prio, 1, keep_defer | 2u);
   }
 
   // snapshot of the state, restored after every candidate

@@ -183,6 +183,27 @@ __device__ __forceinline__ double chi2_sample(const Chi2Consts &c, uint32_t mode
   return __dadd_rn(__dadd_rn(t1, __dmul_rn(c.b, x)), c.nu);
 }
 
+// The chi-square sample of chi2_sample() with the mode chosen by selects
+// rather than branches (every variant is evaluated; the same operations, so
+// the same result, for the selected one).
+__device__ __forceinline__ double chi2_sample_sel(const Chi2Consts &c, uint32_t mode, double x) {
+  const double rf = __dadd_rn(x, c.fisher_root);
+  const double fisher = __dmul_rn(__dmul_rn(rf, rf), 0.5);
+  const double rw = __dadd_rn(__dmul_rn(c.wh_c, x), c.wh_shift);
+  const double wh = __dmul_rn(c.nu, __dmul_rn(__dmul_rn(rw, rw), rw));
+  const double t1 = __dmul_rn(c.A, __dsub_rn(__dmul_rn(x, x), 1.0));
+  const double cubic = __dadd_rn(__dadd_rn(t1, __dmul_rn(c.b, x)), c.nu);
+  return mode == kChi2Fisher ? fisher : mode == kChi2WH ? wh : cubic;
+}
+
+// v with its sign bit flipped when m = 0x80000000 (exact, like a negation)
+__device__ __forceinline__ float flip_sign(float v, uint32_t m) {
+  return __uint_as_float(__float_as_uint(v) ^ m);
+}
+__device__ __forceinline__ double flip_sign(double v, uint32_t m) {
+  return __hiloint2double(int(uint32_t(__double2hiint(v)) ^ m), __double2loint(v));
+}
+
 // ---- cross-lane moves of binary64 values --------------------------------------------
 // DPP (data-parallel primitive) reads of another lane's register, as two 32-bit
 // moves.  Controls: quad_perm [1,0,3,2] (0xB1) and [2,3,0,1] (0x4E) exchange
@@ -508,6 +529,137 @@ struct Engine {
     if (DB) cb ^= 1u;
   }
 
+  // The gathers of gather_transform (quadruples) and gather_rotate (pairs,
+  // x[c][h + 2r] = row r's operand of pair h*L + c*BD + tid) on their own, for
+  // pass_finish_from; the plain passes keep their fused forms, whose address
+  // arithmetic the compiler folds better.
+  template <int RB>
+  __device__ __forceinline__ void load_quads(const PassParams &p, T (&x)[NQ][4]) const {
+    LdsT *P = lds_buf(RB);
+    const uint32_t L = len();
+    constexpr uint32_t W = sizeof(T);
+    const uint32_t mask = (L - 1) * W;  // byte offsets within a row
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const uint32_t a = p.alpha[m];
+      const uint32_t first = __umul24(a * W, tid) + p.gamma[m] * W;
+      const uint32_t step = a * bd() * W;
+      using LdsB = __attribute__((address_space(3))) const unsigned char;
+      LdsB *row = reinterpret_cast<LdsB *>(P + uint32_t(m) * L);
+#pragma unroll
+      for (int c = 0; c < NQ; ++c)
+        x[c][m] = *reinterpret_cast<LdsT *>(row + ((first + step * uint32_t(c)) & mask));
+    }
+  }
+
+  template <int RB>
+  __device__ __forceinline__ void load_pairs(const PassParams &p, T (&x)[NQ][4]) const {
+    LdsT *P = lds_buf(RB);
+    const uint32_t L = len();
+    const uint32_t H = 2 * L;
+    constexpr uint32_t W = sizeof(T);
+    const uint32_t mask = (H - 1) * W;
+    using LdsB = __attribute__((address_space(3))) const unsigned char;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const uint32_t a = p.alpha[r];
+      const uint32_t step = a * bd() * W;
+      LdsB *row = reinterpret_cast<LdsB *>(P + uint32_t(r) * H);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t first = __umul24(a * W, tid) + p.gamma[r] * W + a * (uint32_t(h) * L) * W;
+#pragma unroll
+        for (int c = 0; c < NQ; ++c)
+          x[c][h + 2 * r] = *reinterpret_cast<LdsT *>(row + ((first + step * uint32_t(c)) & mask));
+      }
+    }
+  }
+
+  // A pass that also finishes the previous pool, whose values are still in y.
+  // `chain` (register arithmetic only: that pool's scale) comes first in
+  // program order; the values are copied aside; the pass follows with no
+  // branch (the signs of D_k as sign-bit masks); `put` stores the copy last.
+  // With no branch between the chain and the stores, the compiler interleaves
+  // the chain's binary64 latency with the gathers, the transform and the pool
+  // writes.  The results are those of pass() and of emitting the copy.
+  template <bool ROT, bool RENORM, int RB, typename Chain, typename Put>
+  __device__ __forceinline__ void pass_finish_from(const PassParams &p, double g, Chain &&chain,
+                                                   Put &&put) {
+    constexpr int WB = DB ? 1 - RB : RB;
+    chain();
+    T prev[NQ][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) prev[c][m] = y[c][m];
+    T x[NQ][4];
+    if constexpr (ROT) {
+      load_pairs<RB>(p, x);
+    } else {
+      load_quads<RB>(p, x);
+    }
+    if constexpr (RENORM) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) x[c][m] = T(__dmul_rn(double(x[c][m]), g));
+    }
+    if constexpr (ROT) {
+      const T cT = T(p.c), sT = T(p.s);
+#pragma unroll
+      for (int c = 0; c < NQ; ++c)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) rotate(cT, sT, x[c][h], x[c][h + 2], y[c][h], y[c][h + 2]);
+    } else {
+      // D_k: a and d negated for k = 1, 2; b for k = 1, 3; c for k = 2, 3
+      const uint32_t k = p.k;
+      const uint32_t sa = (k == 1 || k == 2) ? 0x80000000u : 0u;
+      const uint32_t sb = (k & 1u) ? 0x80000000u : 0u;
+      const uint32_t sc = (k >= 2) ? 0x80000000u : 0u;
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) {
+        const T a = flip_sign(x[c][0], sa), b = flip_sign(x[c][1], sb);
+        const T cc = flip_sign(x[c][2], sc), d = flip_sign(x[c][3], sa);
+        quad<0>(a, b, cc, d, y[c]);
+      }
+    }
+    if (!DB) __syncthreads();
+    T *W = buf(WB);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) W[pos(m, c)] = y[c][m];
+    put(prev);
+  }
+
+  template <bool ROT, bool RENORM, typename Chain, typename Put>
+  __device__ __forceinline__ void pass_finish(const PassParams &p, double g, Chain &&chain,
+                                              Put &&put) {
+    if (DB && cb != 0) {
+      pass_finish_from<ROT, RENORM, 1>(p, g, chain, put);
+    } else {
+      pass_finish_from<ROT, RENORM, 0>(p, g, chain, put);
+    }
+    if (DB) cb ^= 1u;
+  }
+
+  // Positions 0 .. n-2 of a pool held in v (the layout of y), as
+  // T(v * fT) (+ muT when mu, a select), to out[obase + i].
+  template <typename O>
+  __device__ __forceinline__ void put_whole(const T (&v)[NQ][4], O *__restrict__ out,
+                                            uint64_t obase, T fT, bool mu, T muT) const {
+    const uint32_t L = len();
+    O *dst = out + obase + tid;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) {
+        const T s = v[c][m] * fT;
+        const O o = Cast<O>::from(mu ? T(s + muT) : s);
+        if (m < 3 || c < NQ - 1 || tid < bd() - 1) dst[uint32_t(m) * L + uint32_t(c) * bd()] = o;
+      }
+  }
+
   // the pool's last element (the withheld one), after the barrier that
   // published the pass writes
   __device__ __forceinline__ T last() const { return cur()[pool_n() - 1]; }
@@ -781,9 +933,16 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
 // the withheld value f * P[n-1] feeds the next sample.  The stored pool is
 // never scaled.  Starts and ends without a barrier of its own: the caller
 // separates two items on one workgroup by a barrier.
-template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, bool STATS, bool ROT>
+//
+// DEFER (no statistics; used without thinning): each pool's scale and
+// emission run inside the next pool's first pass (pass_finish), where the
+// binary64 chain of the scale overlaps the pass's LDS and ALU latency; the
+// last pool is finished after the loop.  Same values, same order of stores.
+template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, bool STATS, bool ROT,
+          bool DEFER = false>
 __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem, uint32_t s,
                                           uint64_t count, uint64_t obase, uint32_t req = 0) {
+  static_assert(!(DEFER && STATS), "the deferred form carries no statistics");
   StreamHdr *h = a.c.hdr + s;
   const uint32_t n = h->n;
   auto e = make_engine<T, NQ, SMALL, DB>(smem, n);
@@ -869,7 +1028,72 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   const uint32_t K = a.c.K;
   uint32_t k_mod = K ? uint32_t(k % K) : 0u;
   const bool rescale = a.c.chi2 != kChi2Off;
-  while (count > 0) {
+  bool deferred = false;
+  if constexpr (DEFER) {
+    if (t == 1) {
+      deferred = true;
+      // kernel-argument values the chain needs, read before the loop
+      const Chi2Consts ccv = cc;
+      const uint32_t mode = a.c.chi2;
+      const double sigma = a.c.sigma;
+      const uint32_t R = a.c.R;
+      const uint64_t pools = count == 0 ? 0 : (count - 1) / (n - 1) + 1;
+      double pq = 0.0, plast = 0.0;  // Q and element n-1 of the pool awaiting its scale
+      bool bad = false;
+      T fT = T(0);
+      // the scale of the pool awaiting it: register arithmetic, no branch
+      auto chain = [&]() {
+        const double S = chi2_sample_sel(ccv, mode, x_current ? plast : xnext);
+        const double fk = rescale ? __dsqrt_rn(__ddiv_rn(S, pq)) : 1.0;
+        f = fk;
+        xnext = __dmul_rn(fk, plast);
+        fT = unit_sigma ? T(fk) : T(__dmul_rn(fk, sigma));
+      };
+      auto put = [&](const T (&v)[NQ][4]) { e.put_whole(v, out, obase, fT, has_mu, muT); };
+      for (uint64_t j = 0; j < pools; ++j) {
+        const bool renorm = k > 0 && K > 0 && k_mod == 0;
+        double g = 1.0;
+        if (renorm) g = __dsqrt_rn(__ddiv_rn(nd, qlast));
+        for (uint32_t r = 0; r < R; ++r) {
+          const uint64_t u1 = xs_next(xs);
+          const uint64_t u2 = xs_next(xs);
+          const PassParams p = decode_for<ROT>(u1, u2, e.len());
+          if (r == 0 && j > 0) {
+            // pool j-1 is finished here: its n-1 values all go out
+            if (renorm)
+              e.template pass_finish<ROT, true>(p, g, chain, put);
+            else
+              e.template pass_finish<ROT, false>(p, g, chain, put);
+            obase += n - 1;
+            count -= n - 1;
+          } else {
+            e.template pass<ROT>(p, renorm && r == 0, g);
+          }
+          if (r + 1 < R) __syncthreads();
+        }
+        pq = e.sumsq();
+        plast = double(e.last());
+        bad |= !(pq > 0.0) || !(pq < __builtin_huge_val());
+        qlast = pq;
+        k += 1;
+        if (K) k_mod = k_mod + 1 == K ? 0u : k_mod + 1;
+      }
+      if (pools > 0) {
+        // the last pool: its scale, then the values the request still wants
+        chain();
+        const uint32_t take = take_of(count, n - 1);
+        if (has_mu)
+          e.template emit<NT, false, true>(out, obase, 0, take, fT, &sa, muT);
+        else
+          e.template emit<NT, false, false>(out, obase, 0, take, fT, &sa, muT);
+        cursor = take;
+        obase += take;
+        count -= take;
+      }
+      if (bad && e.tid == 0) atomicOr(a.c.err, 1u);
+    }
+  }
+  while (!deferred && count > 0) {
     const bool renorm = k > 0 && K > 0 && k_mod == 0;
     double g = 1.0;
     if (renorm) g = __dsqrt_rn(__ddiv_rn(nd, qlast));
@@ -1019,16 +1243,42 @@ __global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
   }
 }
 
-template <typename T, typename O, int NQ, int MAXNQ, bool DB, bool NT, bool STATS, bool ROT>
+// The deferred form for latency-bound launches (few streams): one item per
+// workgroup, two LDS buffers, no statistics.
+template <typename T, typename O, int NQ, bool ROT>
+__global__ __launch_bounds__(kBlock) void k_fill_defer(FillArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t j = blockIdx.x;
+  if (j >= a.nitems) return;
+  uint32_t s;
+  uint64_t count, obase;
+  if (a.items) {
+    const WorkItem it = a.items[j];
+    s = it.stream;
+    count = it.count;
+    obase = it.out_off;
+  } else {
+    s = a.affine_s0 + j;
+    count = a.count_each;
+    obase = uint64_t(j) * a.count_each;
+  }
+  if (count == 0) return;
+  fill_item<T, O, NQ, false, true, false, false, ROT, true>(a, smem, s, count, obase);
+}
+
+template <typename T, typename O, int NQ, int MAXNQ, bool DB, bool NT, bool STATS, bool ROT,
+          bool DEFER = false>
 __device__ __forceinline__ void item_as(const FillArgs &a, unsigned char *smem, const WorkItem &it) {
-  fill_item<T, O, NQ, false, DB, NT, STATS, ROT>(a, smem, it.stream, it.count, it.out_off, it.req);
+  fill_item<T, O, NQ, false, DB, NT, STATS, ROT, DEFER>(a, smem, it.stream, it.count, it.out_off,
+                                                        it.req);
 }
 
 // Persistent form: a fixed grid of workgroups pops work items (pool sizes
 // 1024 .. 1024*MAXNQ, mixed) from a device counter in the order of the list
 // (the host sorts it longest first).  Every workgroup leaves the loop once the
 // counter passes the end of the list.
-template <typename T, typename O, int MAXNQ, bool DB, bool NT, bool STATS, bool ROT>
+template <typename T, typename O, int MAXNQ, bool DB, bool NT, bool STATS, bool ROT,
+          bool DEFER = false>
 __global__ __launch_bounds__(kBlock) void k_fill_persistent(FillArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   // the last 8 bytes of the allocation: the largest pool's spare broadcast
@@ -1054,8 +1304,10 @@ __global__ __launch_bounds__(kBlock) void k_fill_persistent(FillArgs a) {
       continue;
     }
     switch (a.c.hdr[it.stream].n) {
-      case 1024: item_as<T, O, 1, MAXNQ, DB, NT, STATS, ROT>(a, smem, it); break;
-      case 2048: if constexpr (MAXNQ >= 2) item_as<T, O, 2, MAXNQ, DB, NT, STATS, ROT>(a, smem, it); break;
+      // deferred form for pools of up to 2048 (the long chains of small pools);
+      // larger pools keep the plain loop, whose registers set the occupancy
+      case 1024: item_as<T, O, 1, MAXNQ, DB, NT, STATS, ROT, DEFER>(a, smem, it); break;
+      case 2048: if constexpr (MAXNQ >= 2) item_as<T, O, 2, MAXNQ, DB, NT, STATS, ROT, DEFER>(a, smem, it); break;
       case 4096: if constexpr (MAXNQ >= 4) item_as<T, O, 4, MAXNQ, DB, NT, STATS, ROT>(a, smem, it); break;
       case 8192: if constexpr (MAXNQ >= 8) item_as<T, O, 8, MAXNQ, DB, NT, STATS, ROT>(a, smem, it); break;
       default: if constexpr (MAXNQ >= 16) item_as<T, O, 16, MAXNQ, DB, NT, STATS, ROT>(a, smem, it); break;

@@ -112,6 +112,7 @@ struct FillArgs {
   uint32_t variant = 0;             // non-semantic kernel variant (wn_tuning)
   uint32_t *counter = nullptr;      // persistent form: next work item (reset by the launch)
   uint32_t prio_items = 0;          // persistent form: items [0, prio_items) run at priority 3
+  uint32_t defer = 0;               // 1: the deferred form where it applies (latency-bound)
   StatsPartial *partials = nullptr; // fused statistics: one partial per request, or null
   StatsOut *stats = nullptr;        // fused statistics: histogram and tails accumulate here
 };

@@ -96,9 +96,35 @@ hipError_t fill_v(const FillArgs &a, hipStream_t st) {
   return fill_t<T, O, NQ, false, false, false>(a, st);
 }
 
+// The deferred form (each pool's scale and emission inside the next pool's
+// first pass), without statistics or thinning: one-size launches of pools of
+// 1024 or 2048 values (at 4096 the copy of the finished pool costs more than
+// the overlap saves), and persistent launches whose pools are at most 4096
+// (items of 4096 there keep the plain loop).
+inline bool defer_applies(const FillArgs &a, uint32_t max_n, uint32_t limit) {
+  return a.defer && !a.partials && a.c.stride == 1 && max_n >= 1024 && max_n <= limit;
+}
+
+template <typename T, typename O, int NQ, bool ROT>
+hipError_t defer_t(const FillArgs &a, hipStream_t st) {
+  const size_t lds = lds_bytes_for<T>(a.c.n, true, false);
+  auto kern = k_fill_defer<T, O, NQ, ROT>;
+  hipError_t e = prepare(kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(a.nitems), dim3(kBlock), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, typename O, bool ROT>
+hipError_t defer_n(const FillArgs &a, hipStream_t st) {
+  return a.c.n == 1024 ? defer_t<T, O, 1, ROT>(a, st) : defer_t<T, O, 2, ROT>(a, st);
+}
+
 template <typename T, typename O>
 hipError_t fill_n(const FillArgs &a, hipStream_t st) {
   if (a.nitems == 0) return hipSuccess;
+  if (defer_applies(a, a.c.n, 2048))
+    return a.c.transform ? defer_n<T, O, true>(a, st) : defer_n<T, O, false>(a, st);
   switch (a.c.n) {
     case 1024: return fill_v<T, O, 1>(a, st);
     case 2048: return fill_v<T, O, 2>(a, st);
@@ -120,10 +146,10 @@ hipError_t fill_n(const FillArgs &a, hipStream_t st) {
 // can be resident); resets a.counter first (a kernel, not a memset, so that
 // the two launches can be captured in a graph).
 template <typename T, typename O, int MAXNQ, bool DB, bool NT, bool STATS = false,
-          bool ROT = false>
+          bool ROT = false, bool DEFER = false>
 hipError_t persistent_t(const FillArgs &a, uint32_t grid, hipStream_t st) {
   const size_t lds = lds_bytes_for<T>(1024u * MAXNQ, DB, STATS);
-  auto kern = k_fill_persistent<T, O, MAXNQ, DB, NT, STATS, ROT>;
+  auto kern = k_fill_persistent<T, O, MAXNQ, DB, NT, STATS, ROT, DEFER>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
   if (grid == 0) {  // as many workgroups as can be resident at once
@@ -175,6 +201,9 @@ hipError_t persistent_v(const FillArgs &a, uint32_t grid, hipStream_t st) {
 template <typename T, typename O>
 hipError_t persistent_n(const FillArgs &a, uint32_t max_n, uint32_t grid, hipStream_t st) {
   if (a.nitems == 0) return hipSuccess;
+  if (defer_applies(a, max_n, 4096))  // two LDS buffers of the largest pool fit for both types
+    return a.c.transform ? persistent_t<T, O, 4, true, false, false, true, true>(a, grid, st)
+                         : persistent_t<T, O, 4, true, false, false, false, true>(a, grid, st);
   if (max_n <= 4096) return persistent_v<T, O, 4>(a, grid, st);
   return persistent_v<T, O, 16>(a, grid, st);
 }

@@ -51,7 +51,8 @@ class wn_tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("lds_double_buffer", C.c_uint32),
                 ("nontemporal_stores", C.c_uint32), ("waves_per_simd", C.c_uint32),
                 ("wgs_per_cu", C.c_uint32), ("use_graph", C.c_uint32),
-                ("long_priority_pct", C.c_uint32), ("streams_per_wg", C.c_uint32)]
+                ("long_priority_pct", C.c_uint32), ("streams_per_wg", C.c_uint32),
+                ("defer_emission", C.c_uint32)]
 
 
 HIST_BINS = 4096
@@ -319,8 +320,11 @@ class Generator:
         return st
 
     def set_tuning(self, lds_double_buffer=None, nontemporal_stores=None, waves_per_simd=None,
-                   wgs_per_cu=None, use_graph=None, long_priority_pct=None, streams_per_wg=None):
+                   wgs_per_cu=None, use_graph=None, long_priority_pct=None, streams_per_wg=None,
+                   defer_emission=None):
         t = self.tuning()
+        if defer_emission is not None:
+            t.defer_emission = int(defer_emission)
         if streams_per_wg is not None:
             t.streams_per_wg = int(streams_per_wg)
         if long_priority_pct is not None:
