@@ -227,7 +227,7 @@ wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t);
 wn_status wn_get_tuning(wn_gen *g, wn_tuning *t);
 
 /* Autotune the launch choices for one request shape: run the request once per
- * candidate (LDS buffering, store kind, register cap, streams per workgroup;
+ * candidate (LDS buffering, store kind, streams per workgroup, deferred emission;
  * for persistent launches grid size and long-item priority),
  * timed with HIP events on hip_stream, restoring the generator's state after
  * each run, and keep the fastest.  The generator's state is unchanged on

@@ -89,17 +89,28 @@ def uneven(W, inputs, stream):
     ms_default = _time(lambda: g.fill_into(out, w["streams"], w["counts"], stream), stream)
     t = g.autotune(out, w["streams"], w["counts"], stream)
     ms_tuned = _time(lambda: g.fill_into(out, w["streams"], w["counts"], stream), stream)
-    j = int(np.argmax(w["counts"]))
-    one = torch.empty(int(w["counts"][j]), dtype=torch.float32, device="cuda")
-    ms_one = _time(lambda: g.fill_into(one, [j], [int(w["counts"][j])], stream), stream)
+    # the chain of one stream alone: the longest request of each pool size (a
+    # small pool costs more per value, so the longest request is not always the
+    # longest chain)
+    chains = []
+    for n in np.unique(w["pool_n"]):
+        idx = np.nonzero(w["pool_n"] == n)[0]
+        j = int(idx[np.argmax(w["counts"][idx])])
+        one = torch.empty(int(w["counts"][j]), dtype=torch.float32, device="cuda")
+        ms_one = _time(lambda: g.fill_into(one, [j], [int(w["counts"][j])], stream), stream)
+        chains.append({"stream": j, "pool_n": int(n), "count": int(w["counts"][j]),
+                       "ms_alone": ms_one})
+        del one
     g.close()
     return {"total_normals": total, "ms_default": ms_default, "ms_tuned": ms_tuned,
             "normals_per_s_tuned": total / ms_tuned * 1e3,
             "tuning": {"lds_double_buffer": t.lds_double_buffer,
                        "nontemporal_stores": t.nontemporal_stores,
-                       "wgs_per_cu": t.wgs_per_cu, "use_graph": t.use_graph},
-            "longest_stream": {"stream": j, "pool_n": int(w["pool_n"][j]),
-                               "count": int(w["counts"][j]), "ms_alone": ms_one}}
+                       "wgs_per_cu": t.wgs_per_cu, "use_graph": t.use_graph,
+                       "long_priority_pct": t.long_priority_pct,
+                       "defer_emission": t.defer_emission},
+            "longest_chain_ms": max(c["ms_alone"] for c in chains),
+            "longest_streams": chains}
 
 
 def precision(W, inputs, stream):
