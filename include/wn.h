@@ -218,19 +218,21 @@ wn_status wn_get_stream(wn_gen *g, uint32_t s, wn_stream_info *info, void *pool_
 
 /* Set or read the generator's launch choices.  wn_set_tuning validates the
  * struct (WN_EINVAL on a bad size, a flag other than 0/1, waves_per_simd other
- * than 0/5/6/8 or set with nontemporal_stores, or wgs_per_cu > 16) and applies
- * to later calls.  Binary32 pools of
+ * than 0/5/6/8 or set with nontemporal_stores, wgs_per_cu > 16,
+ * long_priority_pct > 100, streams_per_wg outside 1..16 or defer_emission > 3)
+ * and applies to later calls.  Binary32 pools of
  * 1024..8192 values have every choice; other shapes, and the plane-rotation
  * family (one launch variant), ignore them.  Defaults: the choices measured
  * fastest for binary32 pools on MI355X. */
 wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t);
 wn_status wn_get_tuning(wn_gen *g, wn_tuning *t);
 
-/* Autotune the launch choices for one request shape: run the request once per
+/* Autotune the launch choices for one request shape: run the request twice per
  * candidate (LDS buffering, store kind, streams per workgroup, deferred emission;
- * for persistent launches grid size and long-item priority),
- * timed with HIP events on hip_stream, restoring the generator's state after
- * each run, and keep the fastest.  The generator's state is unchanged on
+ * for persistent launches grid size and long-item priority), timed with HIP
+ * events on hip_stream, restoring the generator's state after each run; then
+ * the three fastest five times each in turn, and keep the one with the lowest
+ * median.  The generator's state is unchanged on
  * return; `out` (same contract as wn_fill) is used as scratch and holds no
  * defined values afterwards.  *best (nullable) receives the choice, which is
  * also applied.  Synchronous.  Allocates a temporary copy of the state.
