@@ -99,6 +99,18 @@ def cpu_baseline(w, target_seconds):
         dt = time.perf_counter() - t0
         if dt >= target_seconds:
             break
+    # the same on one core: 16 of the streams, about two seconds
+    k1 = min(k, 16)
+    g.fill(streams[:k1], [per] * k1, threads=1)
+    calls1 = 0
+    t1 = time.perf_counter()
+    while True:
+        g.fill(streams[:k1], [per] * k1, threads=1)
+        calls1 += 1
+        dt1 = time.perf_counter() - t1
+        if dt1 >= 2.0:
+            break
+    g.fill(streams[:0], [], threads=threads)  # the oracle's thread count back to all cores
     cpu = "unknown CPU"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -109,7 +121,10 @@ def cpu_baseline(w, target_seconds):
             "kind": "oracle", "cpu": cpu,
             "sample": f"streams 0..{k - 1} of {w['num_streams']} (pool 4096 f32, R=2): "
                       f"{calls} continuing calls of {per} values per stream after an untimed "
-                      f"seeding call, {dt:.1f} s wall on {threads} threads"}
+                      f"seeding call, {dt:.1f} s wall on {threads} threads",
+            "one_core": {"value": calls1 * k1 * per / dt1, "unit": "normals/s",
+                         "sample": f"streams 0..{k1 - 1}: {calls1} continuing calls of {per} "
+                                   f"values per stream, {dt1:.1f} s wall on 1 thread"}}
 
 
 def time_launch(fn, stream, reps=3, warmup=1):
