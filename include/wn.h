@@ -227,12 +227,13 @@ wn_status wn_get_stream(wn_gen *g, uint32_t s, wn_stream_info *info, void *pool_
 wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t);
 wn_status wn_get_tuning(wn_gen *g, wn_tuning *t);
 
-/* Autotune the launch choices for one request shape: run the request twice per
- * candidate (LDS buffering, store kind, streams per workgroup, deferred emission;
- * for persistent launches grid size and long-item priority), timed with HIP
- * events on hip_stream, restoring the generator's state after each run; then
- * the three fastest five times each in turn, and keep the one with the lowest
- * median.  The generator's state is unchanged on
+/* Autotune the launch choices for one request shape.  A measurement of a
+ * candidate (LDS buffering, store kind, streams per workgroup, deferred
+ * emission; for persistent launches grid size and long-item priority) runs the
+ * request once untimed and three times back to back, timed with HIP events on
+ * hip_stream, then restores the generator's state.  Every candidate is measured
+ * twice (the better counts), the three fastest five more times each in turn,
+ * and the one with the lowest median is kept.  The generator's state is unchanged on
  * return; `out` (same contract as wn_fill) is used as scratch and holds no
  * defined values afterwards.  *best (nullable) receives the choice, which is
  * also applied.  Synchronous.  Allocates a temporary copy of the state.

@@ -938,16 +938,22 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
     cleanup();
     return hip_fail(e, "wn_autotune: snapshot");
   }
-  // one timed run of a candidate; the state is restored afterwards
+  // One measurement of a candidate: an untimed call, then the mean of three
+  // calls back to back, as continuing calls run (timing a call right after the
+  // state restore favoured launch shapes that are slower in steady state); the
+  // state is restored afterwards.
   auto time_once = [&](const wn_tuning &t, float *ms) -> wn_status {
     wn_set_tuning(g, &t);
-    if ((e = hipEventRecord(t0, st)) != hipSuccess) return WN_EDEVICE;
     wn_status r = enqueue_fill(g, nreq, streams, counts, out, out_dtype, st);
     if (r != WN_OK) return r;
+    if ((e = hipEventRecord(t0, st)) != hipSuccess) return WN_EDEVICE;
+    for (int i = 0; i < 3; ++i)
+      if ((r = enqueue_fill(g, nreq, streams, counts, out, out_dtype, st)) != WN_OK) return r;
     if ((e = hipEventRecord(t1, st)) != hipSuccess || (e = restore()) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess ||
         (e = hipEventElapsedTime(ms, t0, t1)) != hipSuccess)
       return WN_EDEVICE;
+    *ms /= 3.f;
     return WN_OK;
   };
   auto give_up = [&](wn_status r) -> wn_status {
