@@ -28,18 +28,18 @@ if ROOT not in sys.path:
 
 
 def _time(fn, stream, reps=3, warmup=1):
+    """Mean duration (ms) of fn() over `reps` calls enqueued back to back on
+    `stream` after `warmup` untimed ones (steady state, as continuing calls run)."""
     import torch
     for _ in range(warmup):
         fn()
-    ts = []
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
     for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
         fn()
-        b.record(stream)
-        b.synchronize()
-        ts.append(a.elapsed_time(b))
-    return sorted(ts)[len(ts) // 2]
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
 
 
 def plain(W, inputs, stream):
