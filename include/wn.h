@@ -199,6 +199,15 @@ typedef struct {
  * one pool in ten holds such a value.  Host only; NaN for an unsupported n. */
 double wn_extreme_threshold(uint32_t n);
 
+/* The chi-square constants the generator uses for pools of n values (Section
+ * 5.5; host only, no device needed).  out (6 doubles, caller-owned) receives
+ * nu = n; A, the small root of A^3 - 3 nu A + 2 nu = 0 (eight Newton steps
+ * from 2/3); b = sqrt(2 (nu - A^2)); the Fisher root sqrt(2 nu - 1); and the
+ * Wilson-Hilferty scale sqrt(2 / (9 nu)) and shift 1 - 2 / (9 nu).
+ * Errors: WN_EINVAL for a NULL out or a pool size the generator does not take
+ * (out is then untouched). */
+wn_status wn_chi2_constants(uint32_t n, double *out);
+
 /* wn_fill plus fused statistics of the emitted values into `stats`
  * (caller-owned device memory, 8-byte aligned, sizeof(wn_stats); overwritten).
  * Same semantics and outputs as wn_fill; every count must be below 2^32.

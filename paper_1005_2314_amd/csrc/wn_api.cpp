@@ -253,6 +253,21 @@ double wn_extreme_threshold(uint32_t n) {
   return extreme_threshold(n);
 }
 
+wn_status wn_chi2_constants(uint32_t n, double *out) {
+  if (!out) return fail(WN_EINVAL, "wn_chi2_constants: out is NULL");
+  if (n < 16 || n > 16384 || !is_pow2(n))
+    return fail(WN_EINVAL, "wn_chi2_constants: pool size %u is not a power of two in [16, 16384]",
+                n);
+  const wn::Chi2Consts c = chi2_consts(n);
+  out[0] = c.nu;
+  out[1] = c.A;
+  out[2] = c.b;
+  out[3] = c.fisher_root;
+  out[4] = c.wh_c;
+  out[5] = c.wh_shift;
+  return WN_OK;
+}
+
 const char *wn_last_error(void) { return g_last_error.c_str(); }
 
 wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {

@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "WN_OK", 1: "WN_EINVAL", 2: "WN_ENOMEM", 3: "WN_EDEVICE", 4: 
 EXPORTED = ("wn_create", "wn_seed", "wn_fill", "wn_sync", "wn_get_stream", "wn_destroy",
             "wn_state_size", "wn_save_state", "wn_load_state",
             "wn_last_error", "wn_version", "wn_set_tuning", "wn_get_tuning", "wn_autotune",
-            "wn_fill_stats", "wn_extreme_threshold", "wn_bench_store", "wn_bench_traffic",
+            "wn_fill_stats", "wn_extreme_threshold", "wn_chi2_constants", "wn_bench_store",
+            "wn_bench_traffic",
             "wn_bench_box_muller")
 
 
@@ -119,6 +120,8 @@ def load():
         L.wn_fill_stats.restype = C.c_int
         L.wn_extreme_threshold.argtypes = [C.c_uint32]
         L.wn_extreme_threshold.restype = C.c_double
+        L.wn_chi2_constants.argtypes = [C.c_uint32, C.POINTER(C.c_double)]
+        L.wn_chi2_constants.restype = C.c_int
         L.wn_state_size.argtypes = [vp]
         L.wn_state_size.restype = C.c_size_t
         L.wn_save_state.argtypes = [vp, vp, C.c_size_t]
@@ -223,6 +226,14 @@ _TORCH_DTYPES = None
 def extreme_threshold(n):
     """c_n of the extreme-pool statistics (wn_extreme_threshold); NaN for a bad n."""
     return float(load().wn_extreme_threshold(int(n)))
+
+
+def chi2_constants(n):
+    """(nu, A, b, fisher_root, wh_scale, wh_shift) for pools of n values
+    (wn_chi2_constants); WnError for a bad n."""
+    out = (C.c_double * 6)()
+    check(load().wn_chi2_constants(int(n), out))
+    return tuple(out)
 
 
 def torch_dtype(out_dtype):

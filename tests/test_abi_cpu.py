@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     text = "".join(open(os.path.join(ROOT, "include", h)).read() for h in ("wn.h", "wn_bench.h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(wn_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(wn_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():
@@ -116,3 +116,28 @@ def test_extreme_threshold_is_the_normal_quantile_on_the_grid():
         assert W.extreme_threshold(n) == math.ceil(q * 256) / 256
     for bad in (0, 8, 100, 32768):
         assert math.isnan(W.extreme_threshold(bad))
+
+
+def test_chi2_constants_are_the_oracles_and_solve_their_equations():
+    # host-only entry point; both sides evaluate the same IEEE operations, so the
+    # constants agree bit for bit, and they satisfy the defining equations of
+    # Section 5.5 (a check independent of either implementation)
+    import math
+    import numpy as np
+    from oracle import oracle as O
+    for e in range(4, 15):
+        n = 1 << e
+        nu, A, b, froot, whc, whs = W.chi2_constants(n)
+        oA, ob = O.chi2_consts(n)
+        assert np.float64(A).view(np.uint64) == np.float64(oA).view(np.uint64), n
+        assert np.float64(b).view(np.uint64) == np.float64(ob).view(np.uint64), n
+        assert nu == n
+        assert abs(A ** 3 - 3 * nu * A + 2 * nu) <= 1e-12 * nu  # root of the cubic
+        assert 0.6 < A < 1.0  # the small root (the others are near +-sqrt(3 nu))
+        assert abs(b * b - 2 * (nu - A * A)) <= 1e-12 * nu
+        assert froot == math.sqrt(2 * nu - 1)
+        assert whc == math.sqrt(2 / (9 * nu)) and whs == 1 - 2 / (9 * nu)
+    for bad in (0, 8, 1000, 32768):
+        with pytest.raises(W.WnError) as ei:
+            W.chi2_constants(bad)
+        assert ei.value.status == W.WN_EINVAL
