@@ -978,10 +978,11 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
     cleanup();
     return r == WN_EDEVICE ? hip_fail(e, "wn_autotune: run") : r;
   };
-  // Round 1: every candidate twice (the best of two), after one untimed run
-  // that warms caches and code objects.  Round 2: the three fastest again, five
-  // times each in turn, ranked by their median, so that run-to-run noise of a
-  // few percent does not pick a candidate that is slower on average.
+  // A first measurement of candidate 0 warms caches and code objects and is
+  // dropped.  Then every candidate twice (the better counts), and the three
+  // fastest five more times each in turn, ranked by their median, so that
+  // run-to-run noise of a few percent does not pick a candidate that is slower
+  // on average.
   float ms = 0.f;
   wn_status r = time_once(cands[0], &ms);
   if (r != WN_OK) return give_up(r);
