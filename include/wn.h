@@ -124,7 +124,7 @@ typedef struct {
                                   (0 = as many as can be resident), <= 16 */
   uint32_t use_graph;          /* 1: persistent launches replay a captured HIP graph */
   uint32_t long_priority_pct;  /* persistent launches: 0 = off; else the items whose estimated
-                                  work (pools x pool size) is at least this percentage of the
+                                  work (pools x (pool size + 4096)) is at least this percentage of the
                                   longest item's run at raised wave priority, so that the
                                   longest streams (the critical path) keep their pace while
                                   they share compute units; <= 100 (default 25) */
