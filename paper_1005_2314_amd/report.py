@@ -27,7 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-def _time(fn, stream, reps=3, warmup=1):
+def _time(fn, stream, reps=3, warmup=2):
     """Mean duration (ms) of fn() over `reps` calls enqueued back to back on
     `stream` after `warmup` untimed ones (steady state, as continuing calls run)."""
     import torch
