@@ -187,8 +187,9 @@ def comparators(W, w, out, stream):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (streams shard "
-              "across GPUs with no exchange, but this build measures one GPU)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (streams would "
+              "shard across GPUs with no exchange, but only the one-GPU path exists)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
