@@ -134,8 +134,9 @@ struct wn_gen {
   std::vector<uint8_t> seen;  // duplicate check scratch
   wn::Chi2Consts cc[wn::kNumSizes];  // per pool size 2^4 .. 2^14
   double xthr[wn::kNumSizes];        // extreme-value thresholds, same sizes
-  // launch choices (wn_tuning); defaults: LDS double buffer, graph replay
-  uint32_t variant = 1;
+  // launch choices (wn_tuning); defaults: one LDS pool buffer (faster in steady
+  // state on every workload measured), graph replay
+  uint32_t variant = 0;
   uint32_t wgs_per_cu = 0;
   uint32_t long_priority_pct = 25;
   uint32_t streams_per_wg = 1;
