@@ -29,11 +29,19 @@ if ROOT not in sys.path:
 
 def _time(fn, stream, reps=3, warmup=2):
     """Mean duration (ms) of fn() over `reps` calls enqueued back to back on
-    `stream` after `warmup` untimed ones (steady state, as continuing calls run)."""
+    `stream` after untimed ones (steady state, as continuing calls run): `warmup`
+    calls, then as many as keep the GPU busy for about 50 ms more, since the
+    first calls after an idle host phase run slower while the clocks settle."""
     import torch
     for _ in range(warmup):
         fn()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    fn()
+    b.record(stream)
+    b.synchronize()
+    for _ in range(min(200, int(50.0 / max(a.elapsed_time(b), 0.05)))):
+        fn()
     a.record(stream)
     for _ in range(reps):
         fn()
