@@ -64,6 +64,10 @@ def lib():
         L.orc_sumsq_f32.restype = C.c_double
         L.orc_sumsq_f64.argtypes = [f64p, C.c_uint32]
         L.orc_sumsq_f64.restype = C.c_double
+        L.orc_initial_pool_f32.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, f32p]
+        L.orc_initial_pool_f32.restype = C.c_uint64
+        L.orc_initial_pool_f64.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, f64p]
+        L.orc_initial_pool_f64.restype = C.c_uint64
         L.orc_chi2_consts.argtypes = [C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_chi2_sample.argtypes = [C.c_uint32, C.c_uint32, f64p, f64p, C.c_uint64]
         L.orc_cvt_bf16.argtypes = [f32p, u16p, C.c_uint64]
@@ -164,6 +168,18 @@ def sumsq(P: np.ndarray) -> float:
     if P.dtype == np.float32:
         return float(lib().orc_sumsq_f32(P, P.size))
     return float(lib().orc_sumsq_f64(np.ascontiguousarray(P, np.float64), P.size))
+
+
+def initial_pool(seed: int, stream: int, n: int, pool_dtype: str = "f32"):
+    """Stream `stream`'s pool before renormalisation and warm-up, and the
+    xorshift state after drawing it."""
+    if pool_dtype == "f64":
+        P = np.empty(n, np.float64)
+        xs = lib().orc_initial_pool_f64(seed, stream, n, P)
+    else:
+        P = np.empty(n, np.float32)
+        xs = lib().orc_initial_pool_f32(seed, stream, n, P)
+    return P, int(xs)
 
 
 def chi2_consts(n: int):

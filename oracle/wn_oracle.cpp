@@ -231,10 +231,14 @@ void run_pass(std::vector<T> &P, const PassParams &p, uint32_t hazard,
 
 // ---------------------------------------------------------------------------
 // Sum of squares (§5.5: the pool's sum of squares is what the rescale acts
-// on).  R6: squares and sums in binary64.  The order is fixed:
-//   B = min(256, n/4);  s_j = (((x_j^2 + x_{j+B}^2) + x_{j+2B}^2) + ...)
-//   for j = 0..B-1, then Q = balanced pairwise sum of s_0..s_{B-1} (each node
-//   adds its left half's sum to its right half's sum).
+// on).  R6: squares and sums in binary64, in an order fixed by the pool's own
+// 4 x L shape (the rows and columns the passes use, §5.4), so that the result
+// is a function of the pool alone:
+//   c_q = ((x_{0,q}^2 + x_{1,q}^2) + x_{2,q}^2) + x_{3,q}^2   (column q of the
+//         4 x L pool, rows in order), q = 0..L-1;
+//   Q   = balanced pairwise sum of c_0 .. c_{L-1} in column order (each node
+//         adds its left half's sum to its right half's sum).
+// The paper fixes only the quantity; this order is a choice of the build.
 // ---------------------------------------------------------------------------
 double pairwise_sum(const double *a, uint32_t len) {
   if (len == 1) return a[0];
@@ -244,17 +248,17 @@ double pairwise_sum(const double *a, uint32_t len) {
 
 template <class T>
 double sum_of_squares(const T *P, uint32_t n) {
-  const uint32_t B = std::min<uint32_t>(256u, n / 4);
-  std::vector<double> s(B);
-  for (uint32_t j = 0; j < B; ++j) {
-    double acc = double(P[j]) * double(P[j]);
-    for (uint32_t i = j + B; i < n; i += B) {
-      const double v = double(P[i]);
+  const uint32_t L = n / 4;
+  std::vector<double> col(L);
+  for (uint32_t q = 0; q < L; ++q) {
+    double acc = double(P[q]) * double(P[q]);
+    for (uint32_t m = 1; m < 4; ++m) {
+      const double v = double(P[m * L + q]);
       acc = acc + v * v;
     }
-    s[j] = acc;
+    col[q] = acc;
   }
-  return pairwise_sum(s.data(), B);
+  return pairwise_sum(col.data(), L);
 }
 
 // Rescale the pool so that its sum of squares is n: g = sqrt(n / Q),
@@ -417,6 +421,18 @@ struct Stream {
   std::vector<PoolRecord> trace;
 };
 
+// R8: the initial pool, before any renormalisation: one uniform per element,
+// its top 23 bits shifted to a symmetric half-integer grid,
+// P[i] = ((v >> 41) - 2^22 + 1/2) 2^-22 (exact in binary32).
+template <class T>
+void initial_pool(uint64_t &xs, T *P, uint32_t n) {
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint64_t v = xorshift64_next(xs);
+    const double c = double(int64_t(v >> 41) - (int64_t(1) << 22)) + 0.5;
+    P[i] = T(c * 0x1p-22);
+  }
+}
+
 struct Config {
   uint32_t num_streams;
   uint32_t R;       // passes per emitted pool
@@ -463,11 +479,7 @@ struct Gen {
     st.n = pool_n[s];
     st.xs = stream_state(seed, s);
     st.P.assign(st.n, T(0));
-    for (uint32_t i = 0; i < st.n; ++i) {
-      const uint64_t v = xorshift64_next(st.xs);
-      const double c = double(int64_t(v >> 41) - (int64_t(1) << 22)) + 0.5;
-      st.P[i] = T(c * 0x1p-22);
-    }
+    initial_pool(st.xs, st.P.data(), st.n);
     renormalise(st.P, sum_of_squares(st.P.data(), st.n));
     const uint32_t W = cfg.warmup ? cfg.warmup : warmup_passes(st.n, cfg.transform);
     for (uint32_t w = 0; w < W; ++w) one_pass(st);
@@ -699,6 +711,19 @@ void orc_rotation_pass_f64(double *P, uint32_t n, const uint32_t *alpha, const u
 }
 
 uint32_t orc_warmup_passes(uint32_t n, uint32_t transform) { return warmup_passes(n, transform); }
+
+// Initial pool of stream `stream` (before renormalisation and warm-up);
+// returns the xorshift state after it.
+uint64_t orc_initial_pool_f32(uint64_t seed, uint64_t stream, uint32_t n, float *P) {
+  uint64_t xs = stream_state(seed, stream);
+  initial_pool(xs, P, n);
+  return xs;
+}
+uint64_t orc_initial_pool_f64(uint64_t seed, uint64_t stream, uint32_t n, double *P) {
+  uint64_t xs = stream_state(seed, stream);
+  initial_pool(xs, P, n);
+  return xs;
+}
 
 double orc_sumsq_f32(const float *P, uint32_t n) { return sum_of_squares(P, n); }
 double orc_sumsq_f64(const double *P, uint32_t n) { return sum_of_squares(P, n); }

@@ -313,3 +313,51 @@ def test_current_pool_source_is_fastnorms_choice():
     a.seed(4)
     b.seed(4)
     np.testing.assert_array_equal(a.fill([0, 1], [9000, 9000]), b.fill([0, 1], [9000, 9000]))
+
+
+# ---- which pool renormalises, and with which sum of squares ------------------
+
+@pytest.mark.parametrize("pool", ["f32", "f64"])
+def test_renormalisation_trigger_and_source(pool):
+    """Pool k (k > 0, k mod K = 0) starts by scaling the stored pool by
+    sqrt(n / Q_{k-1}), Q_{k-1} being the sum of squares of pool k-1; other pools
+    start from the stored pool as it is.  Each pool is rebuilt here from the
+    previous state with the pinned pieces (xorshift draws, pass decode, pass,
+    sum of squares) and compared bit for bit; a missing scale at the renormalising
+    pools, and a trigger one pool late (k mod K = 1), are shown to give other
+    bits, so the comparison can fail."""
+    n, R, K = 64, 2, 3
+    T = np.float64 if pool == "f64" else np.float32
+    g = gen(n, R=R, pool=pool, K=K)
+    info, P = g.stream(0)
+    assert info.k == 0 and info.cursor == n - 1
+    checked_renorm = 0
+    for k in range(0, 8):
+        xs, qprev = int(info.xs), float(info.qlast)
+
+        def rebuild(scale_with):
+            Q0 = P.copy()
+            if scale_with is not None:
+                gs = math.sqrt(n / scale_with)
+                Q0 = (Q0.astype(np.float64) * gs).astype(T)
+            draws = O.xorshift64(xs, 2 * R)
+            for r in range(R):
+                kk, a, gm = O.decode(int(draws[2 * r]), int(draws[2 * r + 1]), n // 4)
+                Q0 = O.run_pass(Q0, kk, a, gm)
+            return Q0, int(draws[-1])
+
+        renorm = k > 0 and k % K == 0
+        want, xs_after = rebuild(qprev if renorm else None)
+        g.fill([0], [n - 1])  # exactly one new pool
+        info, P = g.stream(0)
+        assert info.k == k + 1 and info.xs == xs_after
+        np.testing.assert_array_equal(P.view(np.uint8), want.view(np.uint8))
+        assert info.qlast == O.sumsq(want)
+        if renorm:
+            checked_renorm += 1
+            unscaled, _ = rebuild(None)
+            assert not np.array_equal(unscaled, want)
+        if k > 0 and k % K == 1:
+            wrong, _ = rebuild(qprev)  # a trigger at k mod K = 1 scales here
+            assert not np.array_equal(wrong, want)
+    assert checked_renorm == 2

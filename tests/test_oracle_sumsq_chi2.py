@@ -29,11 +29,28 @@ def test_sumsq_exact_on_integers():
     assert O.sumsq(P) == float(np.sum(P.astype(np.int64) ** 2))
 
 
+def _hexf(v):
+    return float.fromhex(v) if v.startswith(("0x", "-0x")) else float(v)
+
+
 def test_sumsq_summation_order_by_hand():
     rows = {r[0]: r[1:] for r in read_golden("sumsq_order.txt")}
-    pool = np.array([float.fromhex(v) if v.startswith("0x") else float(v)
-                     for v in rows["pool"]], np.float32)
+    pool = np.array([_hexf(v) for v in rows["pool"]], np.float32)
     want = float.fromhex(rows["sumsq"][0])
+    assert O.sumsq(pool) == want
+    assert O.sumsq(pool.astype(np.float64)) == want
+
+
+def test_sumsq_summation_order_by_hand_wide_pool():
+    """L = 512 columns: an order built on 256 interleaved running sums (or any
+    other order the fixture lists) gives another value."""
+    rows = read_golden("sumsq_order_2048.txt")
+    n = int(next(r[1] for r in rows if r[0] == "n"))
+    pool = np.zeros(n, np.float32)
+    for r in rows:
+        if r[0] == "at":
+            pool[int(r[1])] = _hexf(r[2])
+    want = float.fromhex(next(r[1] for r in rows if r[0] == "sumsq"))
     assert O.sumsq(pool) == want
     assert O.sumsq(pool.astype(np.float64)) == want
 
@@ -45,6 +62,58 @@ def test_sumsq_drops_nothing():
             P = np.zeros(n, np.float32)
             P[i] = 3.0
             assert O.sumsq(P) == 9.0
+
+
+def _splitmix64_output(seed, k):
+    """Output number k (1-based) of SplitMix64 from `seed`, from its published
+    definition (increment, then two xor-shift-multiply steps and a final xor-shift)."""
+    M = (1 << 64) - 1
+    z = (seed + k * 0x9E3779B97F4A7C15) & M
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+    return z ^ (z >> 31)
+
+
+def _xorshift64_draws(x, count):
+    M = (1 << 64) - 1
+    out = []
+    for _ in range(count):
+        x ^= (x << 13) & M
+        x ^= x >> 7
+        x ^= (x << 17) & M
+        out.append(x)
+    return out
+
+
+def test_initial_pool_by_hand():
+    """The first values of stream 0's initial pool under seed 1, before any
+    renormalisation (the worked values of golden/initial_pool.txt)."""
+    rows = {r[0]: r[1:] for r in read_golden("initial_pool.txt")}
+    seed, stream = int(rows["seed"][0]), int(rows["stream"][0])
+    state = int(rows["state"][0], 16)
+    draws = [int(v, 16) for v in rows["draws"]]
+    want = np.array([_hexf(v) for v in rows["pool"]], np.float64)
+    # the fixture's own arithmetic, restated from the published definitions
+    assert _splitmix64_output(seed, stream + 1) == state
+    assert O.stream_state(seed, stream) == state
+    assert _xorshift64_draws(state, len(draws)) == draws
+    for v, p in zip(draws, want):
+        assert ((v >> 41) - (1 << 22) + 0.5) * 2.0**-22 == p
+    for dt in ("f32", "f64"):
+        P, xs_after = O.initial_pool(seed, stream, 16, dt)
+        np.testing.assert_array_equal(P[: want.size].astype(np.float64), want)
+        assert xs_after == _xorshift64_draws(state, 16)[-1]
+
+
+@pytest.mark.parametrize("n", [16, 1024])
+def test_initial_pool_grid(n):
+    """Every initial value is an odd multiple of 2^-23 in (-1, 1): a half-integer
+    grid symmetric about zero, exact in binary32."""
+    P, _ = O.initial_pool(7, 3, n, "f64")
+    k = P * 2.0**23
+    assert np.all(k == np.round(k)) and np.all(np.abs(P) < 1)
+    assert np.all(np.mod(k, 2) == 1)
+    np.testing.assert_array_equal(O.initial_pool(7, 3, n, "f32")[0].astype(np.float64), P)
 
 
 @pytest.mark.parametrize("n", [16, 64, 1024, 2048, 4096, 16384])
