@@ -15,10 +15,10 @@
 //     lanes of a wave hit 64 distinct LDS banks;
 //   * the results go back to positions m*L + q (consecutive lanes, consecutive
 //     words), again conflict-free;
-//   * thread tid holds exactly the elements i = tid (mod BD), so the binary64
-//     sum of squares in its fixed order (interleaved running sums, then a
-//     balanced tree over the BD running sums) needs no data movement before
-//     the cross-lane tree;
+//   * thread tid holds whole columns q = c*BD + tid of the 4 x L pool, so the
+//     binary64 column sums of the sum of squares (rows in order) need no data
+//     movement; the balanced tree over the L columns then runs through a
+//     wave-local LDS transposition, DPP lane trees and a few LDS slots;
 //   * emission writes, for each (m, c), 64 consecutive output words per wave
 //     straight from registers: coalesced stores with no LDS staging.
 // There is no MFMA here: the transform is a 4-point stencil, not a dense
@@ -238,6 +238,35 @@ __device__ __forceinline__ double wave_pairwise_sum(double v) {
                    __dadd_rn(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
+// Balanced pairwise sum inside each group of G consecutive lanes (G = 4, 8 or
+// 16), lane order; every lane of a group returns its group's sum.  The wave
+// must be fully active (DPP reads other lanes' registers).
+template <int G>
+__device__ __forceinline__ double group_pairwise_sum(double v) {
+  static_assert(G == 4 || G == 8 || G == 16, "groups of 4, 8 or 16 lanes");
+  v = __dadd_rn(v, dpp_f64<0xB1>(v));
+  v = __dadd_rn(v, dpp_f64<0x4E>(v));
+  if constexpr (G >= 8) v = __dadd_rn(v, dpp_f64<0x141>(v));
+  if constexpr (G >= 16) v = __dadd_rn(v, dpp_f64<0x140>(v));
+  return v;
+}
+
+// Balanced pairwise sum of v[0..N) in index order (N a power of two).
+template <int N>
+__device__ __forceinline__ double pairwise(const double *v) {
+  if constexpr (N == 1) {
+    return v[0];
+  } else {
+    return __dadd_rn(pairwise<N / 2>(v), pairwise<N / 2>(v + N / 2));
+  }
+}
+
+// Keeps the compiler from moving LDS accesses across this point.  No
+// instruction is needed: the LDS performs the operations of one wave in the
+// order they are issued, so a lane reads what other lanes of its wave wrote
+// before.
+__device__ __forceinline__ void wave_lds_order() { asm volatile("" ::: "memory"); }
+
 // ---- output casts (round to nearest even) ---------------------------------------
 struct Bf16 {
   uint16_t u;
@@ -336,6 +365,42 @@ struct StatsAcc {
   }
 };
 
+// ---- LDS layout ---------------------------------------------------------------------
+// LDS of one workgroup (all dynamic, from local address 0):
+//   pool buffer(s)              n * sizeof(T), twice with two buffers
+//   sum-of-squares scratch      4 waves x min(NQ, 4) x 64 binary64 (NQ > 1 only)
+//   partial-sum slots           two sets of 4 * NQ binary64, used alternately
+//   2 words for broadcasts
+//   with statistics: 16 slots, 4 flag words and the histogram.
+// Every part grows with n, so a persistent launch sized for its largest pool
+// holds every smaller pool's layout below its own last 8 bytes.
+constexpr size_t kMiscLds = 2 * sizeof(uint64_t);
+
+__host__ __device__ constexpr uint32_t nq_of(uint32_t n) { return n >= 1024 ? n / 1024 : 1u; }
+// columns per thread handled in one round of the sum-of-squares transposition
+__host__ __device__ constexpr uint32_t sq_round(uint32_t nq) { return nq < 4 ? nq : 4u; }
+
+template <typename T>
+__host__ __device__ constexpr size_t pool_lds(uint32_t n, bool db) {
+  return size_t(n) * sizeof(T) * (db ? 2 : 1);
+}
+__host__ __device__ constexpr size_t sq_scratch_lds(uint32_t n) {
+  return nq_of(n) > 1 ? size_t(sq_round(nq_of(n))) * 4 * 64 * sizeof(double) : 0;
+}
+__host__ __device__ constexpr uint32_t slot_set(uint32_t n) { return 4 * nq_of(n); }
+template <typename T>
+__host__ __device__ constexpr size_t slots_off(uint32_t n, bool db) {
+  return pool_lds<T>(n, db) + sq_scratch_lds(n);
+}
+template <typename T>
+__host__ __device__ constexpr size_t misc_off(uint32_t n, bool db) {
+  return slots_off<T>(n, db) + 2 * size_t(slot_set(n)) * sizeof(double);
+}
+template <typename T>
+__host__ __device__ constexpr size_t lds_bytes_for(uint32_t n, bool db, bool stats) {
+  return misc_off<T>(n, db) + kMiscLds + (stats ? kStatsLds : 0);
+}
+
 // ---- the per-workgroup pool engine ------------------------------------------------
 // SMALL: pools with L < 256, launched with BD = L threads and NQ = 1.
 // DB: two LDS pool buffers; a pass reads one and writes the other, so it needs
@@ -343,15 +408,19 @@ struct StatsAcc {
 //
 // Barrier discipline: every LDS pool write is followed by a barrier before the
 // pool is read again; sumsq() ends with a barrier that also publishes the pool
-// writes before it.  Two sumsq() calls must be separated by a barrier (the
-// second one rewrites the partial-sum slots the first one's readers use).
+// writes before it.  Successive sumsq() calls use the two slot sets in turn,
+// so the next call's slot writes never meet this call's slot reads (every
+// wave has read them before it reaches the next call's barrier).
 template <typename T, int NQ, bool SMALL, bool DB>
 struct Engine {
+  static constexpr uint32_t kSet = 4 * NQ;  // partial-sum slots per set
   T *base;      // LDS: pool buffer 0, then buffer 1 when DB
-  double *red;  // LDS, 4 partial sums
+  double *red;  // LDS: two sets of kSet partial-sum slots
+  double *sqs;  // LDS: the sum-of-squares transposition scratch (NQ > 1)
   uint32_t Lr;  // row length for SMALL pools (else the compile-time kBlock * NQ)
   uint32_t tid;
   uint32_t cb;  // buffer holding the pool (0, or 1 when DB)
+  uint32_t rs;  // slot set of the next sumsq() (0 or 1)
   T y[NQ][4];   // y[c][m] = element m*L + c*BD + tid
 
   __device__ __forceinline__ uint32_t len() const { return SMALL ? Lr : kBlock * NQ; }
@@ -664,17 +733,69 @@ struct Engine {
   // published the pass writes
   __device__ __forceinline__ T last() const { return cur()[pool_n() - 1]; }
 
-  // Sum of squares of the pool held in y: running sum over this thread's
-  // elements in increasing index order, then a balanced pairwise tree over
-  // the BD threads (lanes of a wave, then the waves).  Ends with a barrier;
-  // every thread returns the same value.
+  // Sum of squares of the pool held in y, in the order fixed by the pool's
+  // 4 x L shape: column sums c_q = ((x_0q^2 + x_1q^2) + x_2q^2) + x_3q^2, then
+  // the balanced pairwise tree over the L columns in column order, all in
+  // binary64.  Thread tid holds columns q = c*BD + tid (c = 0..NQ-1).
+  //   NQ = 1 (and SMALL): one column per thread; the tree over the threads
+  //   is the tree over the columns.
+  //   NQ > 1: the tree's nodes of 64 columns are the blocks (c, wave)
+  //   = columns c*256 + 64w .. +63.  Each wave writes its column sums to its
+  //   own LDS scratch and reads them back transposed: lane l takes NQ
+  //   consecutive columns of block (c, w), c = l / G, G = 64 / NQ, and sums
+  //   them in-lane; a DPP tree over each group of G lanes gives the block's
+  //   node.  The 4 NQ nodes go to LDS slots in column order (c major, wave
+  //   minor), and every thread finishes the tree over them.
+  // Ends with a barrier; every thread returns the same value.
   __device__ __forceinline__ double sumsq() {
-    double acc = 0.0;
+    double col[NQ];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int c = 0; c < NQ; ++c) {
+      double acc = sq_add(0.0, y[c][0]);
 #pragma unroll
-      for (int c = 0; c < NQ; ++c) acc = sq_add(acc, y[c][m]);
-    return block_sum(acc, red);
+      for (int m = 1; m < 4; ++m) acc = sq_add(acc, y[c][m]);
+      col[c] = acc;
+    }
+    double *slots = red + rs * kSet;
+    rs ^= 1u;
+    if constexpr (NQ == 1) {
+      return block_sum(col[0], slots);
+    } else {
+      constexpr int CR = int(sq_round(NQ));  // columns per thread per round
+      constexpr int G = 64 / NQ;             // lanes per block (c, w)
+      const uint32_t lane = tid & 63u, w = tid >> 6;
+      const uint32_t cl = lane / G, gl = lane % G;  // this lane's block and group slot
+      double *sc = sqs + w * (CR * 64);
+      double node = 0.0;
+#pragma unroll
+      for (int r = 0; r < NQ / CR; ++r) {
+        if (r > 0) wave_lds_order();  // the previous round's reads come first
+#pragma unroll
+        for (int j = 0; j < CR; ++j) sc[j * 64 + lane] = col[r * CR + j];
+        wave_lds_order();
+        if (NQ == CR || cl / CR == uint32_t(r)) {
+          const double *src = sc + (cl % CR) * 64 + gl * NQ;
+          double v[NQ];
+#pragma unroll
+          for (int j = 0; j < NQ; ++j) v[j] = src[j];
+          node = pairwise<NQ>(v);
+        }
+      }
+      if constexpr (G <= 16) {
+        node = group_pairwise_sum<G>(node);
+        if (gl == 0) slots[cl * 4 + w] = node;
+      } else {  // NQ = 2: blocks of 32 lanes, rows of 16 combined by lane reads
+        node = group_pairwise_sum<16>(node);
+        const double b0 = __dadd_rn(readlane_f64(node, 0), readlane_f64(node, 16));
+        const double b1 = __dadd_rn(readlane_f64(node, 32), readlane_f64(node, 48));
+        if (lane < 2) slots[lane * 4 + w] = lane == 0 ? b0 : b1;
+      }
+      __syncthreads();
+      double s[4 * NQ];
+#pragma unroll
+      for (int i = 0; i < 4 * NQ; ++i) s[i] = slots[i];
+      return pairwise<4 * NQ>(s);
+    }
   }
 
   // Balanced pairwise sum of one value per thread over the BD threads in
@@ -800,10 +921,12 @@ template <typename T, int NQ, bool SMALL, bool DB>
 __device__ __forceinline__ Engine<T, NQ, SMALL, DB> make_engine(unsigned char *smem, uint32_t n) {
   Engine<T, NQ, SMALL, DB> e;
   e.base = reinterpret_cast<T *>(smem);
-  e.red = reinterpret_cast<double *>(smem + size_t(n) * sizeof(T) * (DB ? 2 : 1));
+  e.sqs = reinterpret_cast<double *>(smem + pool_lds<T>(n, DB));
+  e.red = reinterpret_cast<double *>(smem + slots_off<T>(n, DB));
   e.Lr = n / 4;
   e.tid = threadIdx.x;
   e.cb = 0;
+  e.rs = 0;
   return e;
 }
 
@@ -821,30 +944,23 @@ __device__ __forceinline__ void flag_fault(uint32_t *err, double Q) {
   if (!(Q > 0.0) || !(Q < __builtin_huge_val())) atomicOr(err, 1u);
 }
 
-// ---- LDS layout ---------------------------------------------------------------------
-// LDS of one workgroup (all dynamic, from local address 0): pool buffer(s),
-// 4 partial-sum slots, 2 words for broadcasts, and with statistics 16 more
-// slots and the histogram.
-constexpr size_t kMiscLds = 2 * sizeof(uint64_t);
-
-template <typename T>
-__host__ __device__ constexpr size_t lds_bytes_for(uint32_t n, bool db, bool stats) {
-  return size_t(n) * sizeof(T) * (db ? 2 : 1) + 4 * sizeof(double) + kMiscLds +
-         (stats ? kStatsLds : 0);
+// ---- LDS regions after the partial-sum slots (offsets from misc_off) ----------------
+// broadcast word w (0 or 1)
+__device__ __forceinline__ uint64_t *misc_word(unsigned char *smem, size_t misc, int w) {
+  return reinterpret_cast<uint64_t *>(smem + misc) + w;
 }
 
-// broadcast word w (0 or 1) after the partial-sum slots
-__device__ __forceinline__ uint64_t *misc_word(unsigned char *smem, size_t pool_bytes, int w) {
-  return reinterpret_cast<uint64_t *>(smem + pool_bytes + 4 * sizeof(double)) + w;
+// the statistics' 16 partial-sum slots (four sets of 4)
+__device__ __forceinline__ double *stats_slots(unsigned char *smem, size_t misc) {
+  return reinterpret_cast<double *>(smem + misc + kMiscLds);
 }
 
-__device__ __forceinline__ uint32_t *stats_flags(unsigned char *smem, size_t pool_bytes) {
-  return reinterpret_cast<uint32_t *>(smem + pool_bytes + 4 * sizeof(double) + kMiscLds +
-                                      16 * sizeof(double));
+__device__ __forceinline__ uint32_t *stats_flags(unsigned char *smem, size_t misc) {
+  return reinterpret_cast<uint32_t *>(stats_slots(smem, misc) + 16);
 }
 
-__device__ __forceinline__ uint32_t *stats_hist(unsigned char *smem, size_t pool_bytes) {
-  return stats_flags(smem, pool_bytes) + 4;
+__device__ __forceinline__ uint32_t *stats_hist(unsigned char *smem, size_t misc) {
+  return stats_flags(smem, misc) + 4;
 }
 
 __device__ __forceinline__ void hist_clear(uint32_t *hist) {
@@ -873,7 +989,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
   const uint32_t s = a.streams[blockIdx.x];
   const uint32_t n = a.c.n;
   auto e = make_engine<T, NQ, SMALL, false>(smem, n);
-  uint64_t &xs_shared = *misc_word(smem, size_t(n) * sizeof(T), 0);
+  uint64_t &xs_shared = *misc_word(smem, misc_off<T>(n, false), 0);
   StreamHdr *h = a.c.hdr + s;
 
   // Initial values from the top 23 bits of successive uniforms:
@@ -955,8 +1071,8 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   uint32_t *xflags = nullptr;
   const uint64_t emitted = count;
   if constexpr (STATS) {
-    sa.hist = stats_hist(smem, size_t(n) * sizeof(T) * (DB ? 2 : 1));
-    xflags = stats_flags(smem, size_t(n) * sizeof(T) * (DB ? 2 : 1));
+    sa.hist = stats_hist(smem, misc_off<T>(n, DB));
+    xflags = stats_flags(smem, misc_off<T>(n, DB));
     hist_clear(sa.hist);  // published by the barrier after the pool load
     tprev = h->tprev;
   }
@@ -1181,7 +1297,7 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   if constexpr (STATS) {
     // the request's moments: a pairwise tree over the threads, one slot set per
     // moment; then the histogram goes to the global one
-    double *slots = e.red + 4 + kMiscLds / sizeof(double);
+    double *slots = stats_slots(smem, misc_off<T>(n, DB));
     const double s1 = e.block_sum(sa.m1, slots);
     const double s2 = e.block_sum(sa.m2, slots + 4);
     const double s3 = e.block_sum(sa.m3, slots + 8);
