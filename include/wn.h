@@ -141,9 +141,12 @@ typedef struct {
 } wn_tuning;
 
 /* Validate cfg, select the device, allocate the per-stream state in device
- * memory (pools and 64-byte headers) and compute the chi-square constants on
- * the host.  *out_gen receives the generator (NULL on failure).
- * Errors: WN_EINVAL (cfg), WN_EDEVICE (no device / bad ordinal), WN_ENOMEM. */
+ * memory (pools of n values, Section 5.1, and 64-byte headers) and compute the
+ * chi-square constants of Section 5.5 on the host.  *out_gen receives the
+ * generator (NULL on failure).
+ * Errors: WN_EINVAL (cfg), WN_EDEVICE (no device / bad ordinal), WN_ENOMEM
+ * (device or host allocation failed, e.g. a state arena larger than the
+ * device memory; nothing stays allocated then). */
 wn_status wn_create(const wn_config *cfg, wn_gen **out_gen);
 
 /* Seed every stream: stream s starts from xorshift64 state = output s+1 of
@@ -152,7 +155,9 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen);
  * source serves for initialisation).  Enqueued on hip_stream. */
 wn_status wn_seed(wn_gen *g, uint64_t seed, void *hip_stream);
 
-/* Generate: request j asks stream streams[j] for counts[j] values; outputs are
+/* Generate (Sections 5.1-5.5: R passes of the transforms per pool, the
+ * chi-square rescale, n-1 values per pool returned and one withheld):
+ * request j asks stream streams[j] for counts[j] values; outputs are
  * concatenated in request order into `out`, device memory owned by the caller
  * of at least sum(counts) elements of out_dtype.  streams/counts are host
  * arrays, read before the call returns.  Streams continue where the previous
@@ -215,6 +220,7 @@ wn_status wn_chi2_constants(uint32_t n, double *out);
  * a count of 2^32 or more. */
 wn_status wn_fill_stats(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
                         void *out, wn_dtype out_dtype, wn_stats *stats, void *hip_stream);
+
 
 /* Wait for the generator's outstanding work and report a fault a kernel
  * flagged since the last check (a non-finite or zero sum of squares):

@@ -35,8 +35,17 @@ wn_status fail(wn_status st, const char *fmt, ...) {
   return st;
 }
 
+// A failed runtime call is reported through the status; hipGetLastError is
+// read here so that the failure is not reported again by a later launch.
 wn_status hip_fail(hipError_t e, const char *what) {
+  (void)hipGetLastError();
   return fail(e == hipErrorOutOfMemory ? WN_ENOMEM : WN_EDEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+wn_status hip_fail(hipError_t e, const char *who, const char *what) {
+  (void)hipGetLastError();
+  return fail(e == hipErrorOutOfMemory ? WN_ENOMEM : WN_EDEVICE, "%s: %s: %s", who, what,
               hipGetErrorString(e));
 }
 
@@ -521,7 +530,7 @@ hipError_t reserve(wn::WorkItem **host, wn::WorkItem **dev, size_t *cap, size_t 
 // graphs are off).
 hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, uint32_t prio_items,
                              uint32_t max_n, void *out, uint32_t dtype, wn::StatsOut *stats,
-                             hipStream_t st) {
+                             wn::StatsPartial *partials, hipStream_t st) {
   wn::FillArgs a;
   a.c = common(g, 0);
   a.items = slot.dev;
@@ -533,7 +542,7 @@ hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, u
   a.counter = slot.counter;
   a.prio_items = prio_items;
   a.defer = (g->defer_emission >> 1) & 1u;
-  a.partials = stats ? g->d_partials : nullptr;
+  a.partials = partials;
   a.stats = stats;
   int dev = 0, cus = 256;
   hipError_t e = hipGetDevice(&dev);
@@ -588,18 +597,23 @@ hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, u
 //  * otherwise, streams with pools >= 1024 go to one persistent launch over a
 //    work list sorted longest first (estimated pools times (pool size + 4096));
 //  * streams with smaller pools go to one launch per pool size.
-wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
-                       void *out, wn_dtype out_dtype, hipStream_t st,
-                       wn::StatsOut *stats = nullptr) {
-  hipError_t e;
-  wn::StatsPartial *partials = stats ? g->d_partials : nullptr;
+// The affine form: streams s0, s0+1, ... with equal counts and one pool size.
+bool is_affine(const wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts) {
   bool affine = nreq > 0;
   for (uint32_t j = 1; j < nreq && affine; ++j)
     affine = streams[j] == streams[0] + j && counts[j] == counts[0];
   if (affine)
     for (uint32_t j = 0; j < nreq && affine; ++j)
       affine = g->pool_n[streams[j]] == g->pool_n[streams[0]];
-  if (affine) {
+  return affine;
+}
+
+// With statistics, `partials` holds one partial per request (zeroed).
+wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
+                       void *out, wn_dtype out_dtype, hipStream_t st,
+                       wn::StatsOut *stats = nullptr, wn::StatsPartial *partials = nullptr) {
+  hipError_t e;
+  if (is_affine(g, nreq, streams, counts)) {
     wn::FillArgs a;
     a.c = common(g, g->pool_n[streams[0]]);
     a.items = nullptr;
@@ -676,7 +690,7 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
       while (prio_items < nbig && order[prio_items].first >= cut) ++prio_items;
     }
     if ((e = launch_persistent(g, slot, nbig, prio_items, max_n, out, uint32_t(out_dtype), stats,
-                               st)) != hipSuccess)
+                               partials, st)) != hipSuccess)
       return hip_fail(e, "wn_fill: persistent launch");
     if ((e = hipEventRecord(slot.done, st)) != hipSuccess) return hip_fail(e, "wn_fill: event");
     slot.pending = true;
@@ -734,6 +748,40 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
   return WN_OK;
 }
 
+wn_status validate_stats(const char *who, uint32_t nreq, const uint64_t *counts,
+                         const wn_stats *stats) {
+  if (!stats || reinterpret_cast<uintptr_t>(stats) % 8 != 0)
+    return fail(WN_EINVAL, "%s: stats is NULL or not 8-byte aligned", who);
+  for (uint32_t j = 0; j < nreq; ++j)
+    if (counts[j] >= (uint64_t(1) << 32))
+      return fail(WN_EINVAL, "%s: request %u counts 2^32 values or more", who, j);
+  return WN_OK;
+}
+
+// The statistics call after validation and ordering: zero the result and
+// max(nreq, 1) partials (kernels, not memsets), fill, reduce, record.
+wn_status enqueue_fill_stats(wn_gen *g, const char *who, uint32_t nreq, const uint32_t *streams,
+                             const uint64_t *counts, void *out, wn_dtype out_dtype,
+                             wn_stats *stats, wn::StatsPartial *partials, uint64_t total,
+                             hipStream_t st) {
+  hipError_t e;
+  const size_t need = std::max<size_t>(nreq, 1);
+  auto *so = reinterpret_cast<wn::StatsOut *>(stats);
+  if ((e = wn::stats_zero(so, st)) != hipSuccess ||
+      (e = wn::zero_words(partials, uint32_t(need * sizeof(wn::StatsPartial) / 8), st)) !=
+          hipSuccess)
+    return hip_fail(e, who, "zero");
+  if (total > 0) {
+    wn_status v = enqueue_fill(g, nreq, streams, counts, out, out_dtype, st, so, partials);
+    if (v != WN_OK) return v;
+  }
+  if ((e = wn::stats_reduce(partials, nreq, so, st)) != hipSuccess)
+    return hip_fail(e, who, "reduce");
+  if ((e = record_last(g, st)) != hipSuccess)
+    return hip_fail(e, who, "event");
+  return WN_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -760,11 +808,7 @@ wn_status wn_fill_stats(wn_gen *g, uint32_t nreq, const uint32_t *streams, const
   uint64_t total = 0;
   wn_status v = validate_fill(g, "wn_fill_stats", nreq, streams, counts, out, out_dtype, &total);
   if (v != WN_OK) return v;
-  if (!stats || reinterpret_cast<uintptr_t>(stats) % 8 != 0)
-    return fail(WN_EINVAL, "wn_fill_stats: stats is NULL or not 8-byte aligned");
-  for (uint32_t j = 0; j < nreq; ++j)
-    if (counts[j] >= (uint64_t(1) << 32))
-      return fail(WN_EINVAL, "wn_fill_stats: request %u counts 2^32 values or more", j);
+  if ((v = validate_stats("wn_fill_stats", nreq, counts, stats)) != WN_OK) return v;
   hipError_t e = hipSetDevice(g->device);
   if (e != hipSuccess) return hip_fail(e, "wn_fill_stats: hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -783,19 +827,8 @@ wn_status wn_fill_stats(wn_gen *g, uint32_t nreq, const uint32_t *streams, const
       return hip_fail(e, "wn_fill_stats: partials");
     g->partials_cap = need;
   }
-  auto *so = reinterpret_cast<wn::StatsOut *>(stats);
-  if ((e = wn::stats_zero(so, st)) != hipSuccess ||
-      (e = wn::zero_words(g->d_partials, uint32_t(need * sizeof(wn::StatsPartial) / 8), st)) !=
-          hipSuccess)
-    return hip_fail(e, "wn_fill_stats: zero");
-  if (total > 0) {
-    v = enqueue_fill(g, nreq, streams, counts, out, out_dtype, st, so);
-    if (v != WN_OK) return v;
-  }
-  if ((e = wn::stats_reduce(g->d_partials, nreq, so, st)) != hipSuccess)
-    return hip_fail(e, "wn_fill_stats: reduce");
-  if ((e = record_last(g, st)) != hipSuccess) return hip_fail(e, "wn_fill_stats: event");
-  return WN_OK;
+  return enqueue_fill_stats(g, "wn_fill_stats", nreq, streams, counts, out, out_dtype, stats,
+                            g->d_partials, total, st);
 }
 
 wn_status wn_sync(wn_gen *g) {

@@ -182,6 +182,7 @@ wn_status wn_bench_store(void *dst, uint64_t bytes, uint32_t width_dwords, void 
   width_dwords &= 0xFFu;
   if (!dst || bytes % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0 ||
       (width_dwords != 1 && width_dwords != 4)) return WN_EINVAL;
+  (void)hipGetLastError();  // an earlier call's error is not this launch's
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const uint64_t nvec = bytes / (4 * width_dwords);
   const int grid = grid_for(nvec / 4);
@@ -200,6 +201,7 @@ wn_status wn_bench_store(void *dst, uint64_t bytes, uint32_t width_dwords, void 
 wn_status wn_bench_traffic(void *state, void *out, uint32_t num_streams, uint32_t pool_n,
                            uint64_t per_stream, void *hip_stream) {
   if (!state || !out || num_streams == 0) return WN_EINVAL;
+  (void)hipGetLastError();  // an earlier call's error is not this launch's
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   auto *s = static_cast<unsigned char *>(state);
   auto *o = static_cast<float *>(out);
@@ -219,6 +221,7 @@ wn_status wn_bench_box_muller(void *out, uint64_t count, wn_dtype out_dtype, uin
   if (!out || count % 4 != 0 || reinterpret_cast<uintptr_t>(out) % 16 != 0) return WN_EINVAL;
   if (out_dtype != WN_F32 && out_dtype != WN_F64) return WN_EINVAL;
   if (out_dtype == WN_F64 && fast) return WN_EINVAL;
+  (void)hipGetLastError();  // an earlier call's error is not this launch's
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const uint64_t nquads = count / 4;
   const uint2 key = make_uint2(uint32_t(seed), uint32_t(seed >> 32));

@@ -15,8 +15,12 @@ namespace {
 template <typename T>
 constexpr bool kPoolF32 = std::is_same_v<T, float>;
 
+// Before a launch: discard an error an earlier runtime call left behind (a
+// failed allocation is reported by the next hipGetLastError, which would
+// otherwise be taken for this launch's status), then allow the LDS size.
 template <typename Kern>
 hipError_t prepare(Kern kern, size_t lds) {
+  (void)hipGetLastError();
   if (lds > 65536)
     return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -162,6 +166,7 @@ hipError_t persistent_t(const FillArgs &a, uint32_t grid, hipStream_t st) {
       return e;
     grid = uint32_t(cus) * uint32_t(per_cu > 0 ? per_cu : 1);
   }
+  (void)hipGetLastError();  // prepare() and the occupancy query may leave one
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, a.counter);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, st, a);

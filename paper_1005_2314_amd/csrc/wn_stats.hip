@@ -76,6 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_stats_reduce(const StatsPartial *p, 
 
 hipError_t zero_words(void *p, uint32_t nwords, hipStream_t s) {
   const uint32_t grid = std::min<uint32_t>(1024u, (nwords + kBlock - 1) / kBlock + 1);
+  (void)hipGetLastError();  // an earlier call's error is not this launch's
   hipLaunchKernelGGL(k_stats_zero, dim3(grid), dim3(kBlock), 0, s, static_cast<uint64_t *>(p),
                      nwords);
   return hipGetLastError();
@@ -87,6 +88,7 @@ hipError_t stats_zero(StatsOut *out, hipStream_t s) {
 
 hipError_t stats_reduce(const StatsPartial *partials, uint32_t nreq, StatsOut *out,
                         hipStream_t s) {
+  (void)hipGetLastError();  // an earlier call's error is not this launch's
   hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(kBlock), 0, s, partials, nreq, out);
   return hipGetLastError();
 }

@@ -145,3 +145,26 @@ def test_load_state_rejects_headers_that_do_not_fit():
         assert ei.value.status == W.WN_EINVAL, (stream, offset)
     # the refusals left the restored state in place
     np.testing.assert_array_equal(to_numpy_bits(g.fill([0, 1, 2], [300, 300, 300])), expect)
+
+
+def test_create_beyond_device_memory_is_enomem_and_leaves_nothing():
+    """A state arena larger than the device's memory (2^24 binary64 pools of
+    16384 values: 2 TiB) fails with WN_ENOMEM, and every allocation made before
+    the failure is released."""
+    import torch
+    torch.cuda.synchronize()
+    free0, total = torch.cuda.mem_get_info()
+    assert 2**24 * 16384 * 8 > total
+    cfg, _ = W.make_config(2**24, 16384, R=1, pool_dtype=W.WN_F64)
+    with pytest.raises(W.WnError) as ei:
+        W.wn_create(cfg)
+    assert ei.value.status == W.WN_ENOMEM
+    assert "allocation" in str(ei.value)
+    free1, _ = torch.cuda.mem_get_info()
+    assert abs(free1 - free0) < 64 << 20  # nothing of the failed arena stays
+    g = W.Generator(4, pool_n=1024, R=1)  # the library still works
+    g.seed(1)
+    y = g.fill(np.arange(4), [100] * 4)
+    torch.cuda.synchronize()
+    assert y.numel() == 400
+    g.close()

@@ -114,6 +114,12 @@ def test_deferred_and_standard_forms_agree_at_scale():
         np.testing.assert_array_equal(outs[0][0], other[0])
         assert_bits_equal(bits(outs[0][1]), bits(other[1]), "pool")
         assert outs[0][2] == other[2]
+    # and the oracle's bits for two of the streams, whole length
+    orc = O.Generator(ns, pool_n=n, R=2)
+    orc.seed(11)
+    for s in (9, 50):
+        want = bits(orc.fill([s], [per]))
+        assert_bits_equal(outs[0][0][s], want, f"deferred at scale, stream {s}")
 
 
 def test_defer_plain_form_full_length():

@@ -1,6 +1,8 @@
 """Precision sweep: binary32 and binary64 pools, binary32/bf16/f16 outputs,
-against the binary64 oracle on sampled streams of the precision workload
-(16384 streams x 2^16, pool 4096, two passes).
+on sampled streams of the full precision workload (16384 streams x 2^16,
+pool 4096, two passes, in the launch the workload runs): bit for bit against
+the oracle of the same pool type, and within stated bounds of the binary64
+oracle.
 
 Bounds: a binary64 pool cast to the output type is the reference rounded once
 more (bf16/f16 through binary32: at most one ulp of the output type); a
@@ -16,7 +18,7 @@ import os
 import numpy as np
 import pytest
 
-from gpu_util import to_numpy_bits
+from gpu_util import WN_TO_ORC, assert_bits_equal, to_numpy_bits
 from oracle import oracle as O
 from paper_1005_2314_amd import inputs
 from paper_1005_2314_amd import wn as W
@@ -63,12 +65,19 @@ def test_precision_sweep_against_binary64_oracle():
     for pool in ("f32", "f64"):
         g = W.Generator(w["num_streams"], pool_n=w["pool_n"], R=w["R"],
                         pool_dtype=W.WN_F64 if pool == "f64" else W.WN_F32)
+        same = O.Generator(w["num_streams"], pool_n=w["pool_n"], R=w["R"], pool_dtype=pool)
         for odt, oname in ((W.WN_F32, "f32"), (W.WN_BF16, "bf16"), (W.WN_F16, "f16")):
+            print(f"precision: pool {pool} -> {oname}, full workload", flush=True)
             g.seed(w["seed"])
             out = g.fill(w["streams"], w["counts"], odt)
             torch.cuda.synchronize()
             got = torch.cat([out[int(s) * per:(int(s) + 1) * per] for s in sample])
-            y = _widen(to_numpy_bits(got), oname)
+            raw = to_numpy_bits(got)
+            # bit for bit against the oracle of the same pool type
+            same.seed(w["seed"])
+            want = same.fill(sample, [per] * len(sample), WN_TO_ORC[odt])
+            assert_bits_equal(raw, want.view(raw.dtype), f"pool {pool} -> {oname}")
+            y = _widen(raw, oname)
             err = np.abs(y - y64)
             ulp = _ulp(y64, oname)
             if pool == "f64":

@@ -228,3 +228,72 @@ def test_pairs_join_only_pools_the_statistics_saw():
         e = orc.trace(int(s_))[:, 5] >= thr
         want += sum(int(e[k] and e[k - 1]) for k in range(len(e) - 2, len(e)))
     assert c.x_pairs == want
+
+
+def test_quality_workload_full_chunk():
+    """One whole chunk of the quality workload as it runs (262144 streams x 2^16
+    values, pool 4096, two passes, statistics fused; a 64 GiB output): sampled
+    streams bit for bit against the oracle, then the fused statistics against
+    the laws the paper fixes: normal moments, the 4096-bin histogram against
+    the normal distribution (chi-square goodness of fit), the pool sums
+    against chi-square with n - 1 degrees of freedom, and successive pools of a
+    stream uncorrelated (Sections 5.5-5.7), each within five standard errors."""
+    import torch
+    from scipy.special import ndtr
+
+    from paper_1005_2314_amd import inputs
+    w = inputs.throughput_quality()
+    ns, per, n = w["num_streams"], int(w["counts"][0]), w["pool_n"]
+    g = W.Generator(ns, pool_n=n, R=w["R"])
+    g.seed(w["seed"])
+    out = torch.empty(ns * per, dtype=torch.float32, device="cuda")
+    buf = g.stats_buffer()
+    print(f"quality chunk: {ns} streams x {per}, statistics on", flush=True)
+    g.fill_stats_into(out, w["streams"], w["counts"], buf)
+    torch.cuda.synchronize()
+    g.sync()
+    st = g.read_stats(buf)
+    sample = inputs.sample_streams(ns, 8)
+    got = to_numpy_bits(torch.cat([out[int(s) * per:(int(s) + 1) * per] for s in sample]))
+    del out
+    torch.cuda.empty_cache()
+    orc = O.Generator(ns, pool_n=n, R=w["R"])
+    orc.seed(w["seed"])
+    want = orc.fill(sample, [per] * len(sample)).view(got.dtype)
+    np.testing.assert_array_equal(got, want)
+
+    N = st.count
+    assert N == ns * per
+    m = [st.moment[k] / N for k in range(4)]
+    var = m[1] - m[0] ** 2
+    mu3 = m[2] - 3 * m[0] * m[1] + 2 * m[0] ** 3
+    mu4 = m[3] - 4 * m[0] * m[2] + 6 * m[0] ** 2 * m[1] - 3 * m[0] ** 4
+    assert abs(m[0]) < 5 * math.sqrt(1 / N)
+    assert abs(var - 1) < 5 * math.sqrt(2 / N)
+    assert abs(mu3 / var**1.5) < 5 * math.sqrt(6 / N)
+    assert abs(mu4 / var**2 - 3) < 5 * math.sqrt(24 / N)
+    # histogram: bin b holds floor(256 y) + 2048 = b, i.e. y in [(b-2048)/256, (b-2047)/256)
+    hist = np.ctypeslib.as_array(st.hist).astype(np.float64)
+    edges = (np.arange(4097) - 2048) / 256.0
+    p = np.diff(ndtr(edges))
+    obs = np.concatenate([[st.below], hist, [st.above]])
+    exp = N * np.concatenate([[ndtr(-8.0)], p, [ndtr(-8.0)]])
+    keep = exp >= 5
+    tail_obs, tail_exp = obs[~keep].sum(), exp[~keep].sum()
+    o = np.concatenate([obs[keep], [tail_obs]])
+    e = np.concatenate([exp[keep], [tail_exp]])
+    chi2 = float(np.sum((o - e) ** 2 / e))
+    dof = o.size - 1
+    assert chi2 < dof + 5 * math.sqrt(2 * dof), (chi2, dof)
+    # pool sums: chi-square with n - 1 degrees of freedom (centred on n - 1)
+    P = st.pools
+    assert P == ns * (per // (n - 1) + 1)
+    tm = st.t_sum / P
+    tv = st.t_sumsq / P - tm * tm
+    assert abs(tm) < 5 * math.sqrt(2 * (n - 1) / P)
+    assert abs(tv / (2 * (n - 1)) - 1) < 5 * math.sqrt(2 / P)
+    corr = (st.t_lag / st.t_pairs - tm * tm) / tv
+    assert st.t_pairs == P - ns
+    assert abs(corr) < 5 / math.sqrt(st.t_pairs), corr
+    # about one pool in ten holds a value at or beyond c_n (Section 5.7)
+    assert 0.085 < st.x_pools / P < 0.105
