@@ -221,6 +221,24 @@ wn_status wn_chi2_constants(uint32_t n, double *out);
 wn_status wn_fill_stats(wn_gen *g, uint32_t nreq, const uint32_t *streams, const uint64_t *counts,
                         void *out, wn_dtype out_dtype, wn_stats *stats, void *hip_stream);
 
+/* wn_fill_stats for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): it
+ * calls no hipMalloc, hipFree or other allocating routine.  Its per-request
+ * partial sums live in one statically allocated device array of
+ * WN_NOALLOC_MAX_REQUESTS entries of 96 bytes (6 MiB), which every device the
+ * library runs on holds until the process ends; wn_create looks up its
+ * address.  Results (outputs and statistics) are those of wn_fill_stats.
+ * Restriction: the requests must take the form that needs no work list,
+ * consecutive stream ids streams[j] = streams[0] + j with one count and one
+ * pool size (one request always qualifies).  All calls on one device share the
+ * array: calls that overlap on one device (different generators on different
+ * streams) race; calls on one generator are ordered as usual.
+ * Errors: as wn_fill_stats; WN_EINVAL also for nreq > WN_NOALLOC_MAX_REQUESTS,
+ * WN_ENOTSUP for any other request form. */
+#define WN_NOALLOC_MAX_REQUESTS 65536u
+wn_status wn_fill_stats_noalloc(wn_gen *g, uint32_t nreq, const uint32_t *streams,
+                                const uint64_t *counts, void *out, wn_dtype out_dtype,
+                                wn_stats *stats, void *hip_stream);
 
 /* Wait for the generator's outstanding work and report a fault a kernel
  * flagged since the last check (a non-finite or zero sum of squares):

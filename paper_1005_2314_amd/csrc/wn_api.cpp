@@ -158,6 +158,7 @@ struct wn_gen {
   hipStream_t capture_stream = nullptr;
   wn::StatsPartial *d_partials = nullptr;  // fused statistics, one per request
   size_t partials_cap = 0;
+  wn::StatsPartial *d_static_partials = nullptr;  // wn_fill_stats_noalloc: the static array
 };
 
 namespace {
@@ -427,6 +428,10 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   if ((e = hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking)) != hipSuccess) {
     release(g);
     return hip_fail(e, "wn_create: capture stream");
+  }
+  if ((e = wn::noalloc_partials(g->device, &g->d_static_partials)) != hipSuccess) {
+    release(g);
+    return hip_fail(e, "wn_create: static partials");
   }
   for (int i = 0; i < wn::kNumSizes; ++i) {
     g->cc[i] = chi2_consts(16u << i);
@@ -829,6 +834,35 @@ wn_status wn_fill_stats(wn_gen *g, uint32_t nreq, const uint32_t *streams, const
   }
   return enqueue_fill_stats(g, "wn_fill_stats", nreq, streams, counts, out, out_dtype, stats,
                             g->d_partials, total, st);
+}
+
+static_assert(wn::kNoAllocRequests == WN_NOALLOC_MAX_REQUESTS, "static partials of wn.h");
+
+wn_status wn_fill_stats_noalloc(wn_gen *g, uint32_t nreq, const uint32_t *streams,
+                                const uint64_t *counts, void *out, wn_dtype out_dtype,
+                                wn_stats *stats, void *hip_stream) {
+  uint64_t total = 0;
+  const char *who = "wn_fill_stats_noalloc";
+  wn_status v = validate_fill(g, who, nreq, streams, counts, out, out_dtype, &total);
+  if (v != WN_OK) return v;
+  if ((v = validate_stats(who, nreq, counts, stats)) != WN_OK) return v;
+  if (nreq > wn::kNoAllocRequests)
+    return fail(WN_EINVAL, "%s: %u requests, at most %u (the statically allocated partials)", who,
+                nreq, wn::kNoAllocRequests);
+  if (nreq > 1 && !is_affine(g, nreq, streams, counts))
+    return fail(WN_ENOTSUP,
+                "%s: the requests must name consecutive streams with one count and one pool "
+                "size (other request lists need a work list, which is allocated)",
+                who);
+  if (!g->d_static_partials)
+    return fail(WN_EDEVICE, "%s: the static partials were not found at wn_create", who);
+  hipError_t e = hipSetDevice(g->device);
+  if (e != hipSuccess) return hip_fail(e, "wn_fill_stats_noalloc: hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if ((e = order_after_last(g, st)) != hipSuccess)
+    return hip_fail(e, "wn_fill_stats_noalloc: ordering");
+  return enqueue_fill_stats(g, who, nreq, streams, counts, out, out_dtype, stats,
+                            g->d_static_partials, total, st);
 }
 
 wn_status wn_sync(wn_gen *g) {

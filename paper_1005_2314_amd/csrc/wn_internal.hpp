@@ -117,6 +117,13 @@ struct FillArgs {
   StatsOut *stats = nullptr;        // fused statistics: histogram and tails accumulate here
 };
 
+// wn_fill_stats_noalloc: the statically allocated partials (wn_noalloc.hip).
+// noalloc_partials returns their device address on `device`, which must be the
+// current device; the first call on a device looks it up.
+constexpr uint32_t kNoAllocRequests = 1u << 16;  // WN_NOALLOC_MAX_REQUESTS
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_partials(int device, StatsPartial **out);
+
 // Fused statistics: zero `out` before a fill, and fold the request partials
 // into it (binary64 sums in a fixed order) after the fill.
 hipError_t stats_zero(StatsOut *out, hipStream_t s);

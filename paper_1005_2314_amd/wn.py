@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "WN_OK", 1: "WN_EINVAL", 2: "WN_ENOMEM", 3: "WN_EDEVICE", 4: 
 EXPORTED = ("wn_create", "wn_seed", "wn_fill", "wn_sync", "wn_get_stream", "wn_destroy",
             "wn_state_size", "wn_save_state", "wn_load_state",
             "wn_last_error", "wn_version", "wn_set_tuning", "wn_get_tuning", "wn_autotune",
-            "wn_fill_stats", "wn_extreme_threshold", "wn_chi2_constants", "wn_bench_store",
+            "wn_fill_stats", "wn_fill_stats_noalloc", "wn_extreme_threshold", "wn_chi2_constants", "wn_bench_store",
             "wn_bench_traffic",
             "wn_bench_box_muller")
 
@@ -118,6 +118,8 @@ def load():
         L.wn_fill_stats.argtypes = [vp, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
                                     vp, C.c_int, vp, vp]
         L.wn_fill_stats.restype = C.c_int
+        L.wn_fill_stats_noalloc.argtypes = L.wn_fill_stats.argtypes
+        L.wn_fill_stats_noalloc.restype = C.c_int
         L.wn_extreme_threshold.argtypes = [C.c_uint32]
         L.wn_extreme_threshold.restype = C.c_double
         L.wn_chi2_constants.argtypes = [C.c_uint32, C.POINTER(C.c_double)]
@@ -300,9 +302,10 @@ class Generator:
     def sync(self):
         wn_sync(self._h)
 
-    def fill_stats_into(self, out, streams, counts, stats, stream=None):
-        """wn_fill_stats into a caller-owned CUDA output tensor; `stats` is a CUDA
-        uint8 tensor of sizeof(wn_stats) bytes (see read_stats)."""
+    def fill_stats_into(self, out, streams, counts, stats, stream=None, noalloc=False):
+        """wn_fill_stats (wn_fill_stats_noalloc with noalloc=True) into a
+        caller-owned CUDA output tensor; `stats` is a CUDA uint8 tensor of
+        sizeof(wn_stats) bytes (see read_stats)."""
         import torch
         dt = {torch.float64: WN_F64, torch.float32: WN_F32, torch.bfloat16: WN_BF16,
               torch.float16: WN_F16}[out.dtype]
@@ -310,7 +313,8 @@ class Generator:
         counts = np.ascontiguousarray(counts, np.uint64)
         if stats.numel() * stats.element_size() < C.sizeof(wn_stats) or not stats.is_cuda:
             raise ValueError("stats must be a CUDA buffer of sizeof(wn_stats) bytes")
-        check(load().wn_fill_stats(self._h, streams.size,
+        fn = load().wn_fill_stats_noalloc if noalloc else load().wn_fill_stats
+        check(fn(self._h, streams.size,
                                    streams.ctypes.data_as(C.POINTER(C.c_uint32)),
                                    counts.ctypes.data_as(C.POINTER(C.c_uint64)),
                                    C.c_void_p(out.data_ptr()), dt,
