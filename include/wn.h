@@ -240,6 +240,70 @@ wn_status wn_fill_stats_noalloc(wn_gen *g, uint32_t nreq, const uint32_t *stream
                                 const uint64_t *counts, void *out, wn_dtype out_dtype,
                                 wn_stats *stats, void *hip_stream);
 
+/* The statistics battery (Sections 5.5-5.7) on one call's (or several
+ * chained calls') wn_stats, host copy, for pools of pool_n values.  Each
+ * statistic is in standard errors of N independent normal values: z[WN_Q_MEAN],
+ * [WN_Q_VAR], [WN_Q_SKEW], [WN_Q_KURT] the first four moments; [WN_Q_HIST]
+ * the histogram's chi-square against the normal law ((chi2 - dof) /
+ * sqrt(2 dof); cells expecting fewer than 5 values merged with the tails);
+ * [WN_Q_POOL_MEAN], [WN_Q_POOL_VAR] the pool sums D_k against chi-square with
+ * n - 1 degrees of freedom; [WN_Q_POOL_LAG] the correlation of successive pool
+ * sums times sqrt(pairs); [WN_Q_EXTREME_PAIRS] adjacent pools both holding an
+ * extreme value against independence (Section 5.7; variance t_pairs p^2
+ * (1 + 2p - 3p^2) for overlapping pairs).  passed = 1 when every |z| <= z_max,
+ * the histogram and the clustering one-sided (only a worse fit than chance,
+ * and only an excess of adjacent extreme pools, fail); failed_mask bit i marks
+ * z[i].
+ * A statistic that cannot be formed (no pairs) is 0.  Host only.
+ * Errors: WN_EINVAL (NULL pointer, bad pool size, z_max <= 0, fewer than two
+ * values or pools). */
+enum {
+  WN_Q_MEAN = 0, WN_Q_VAR, WN_Q_SKEW, WN_Q_KURT, WN_Q_HIST, WN_Q_POOL_MEAN, WN_Q_POOL_VAR,
+  WN_Q_POOL_LAG, WN_Q_EXTREME_PAIRS, WN_QUALITY_NZ
+};
+typedef struct {
+  double z[WN_QUALITY_NZ];
+  uint32_t passed;
+  uint32_t failed_mask;
+} wn_quality;
+wn_status wn_quality_check(const wn_stats *stats, uint32_t pool_n, double z_max, wn_quality *q);
+
+/* Choose the semantic parameters, pool size n and passes per emitted pool R,
+ * from the candidates that pass the statistics battery: Section 5.7 gives a
+ * larger pool and discarded pools (R passes per emitted pool) as the remedies
+ * for finite-pool effects, at a cost in speed.  For each candidate (n, R) (R
+ * only, when base->pool_n gives per-stream sizes) a temporary generator with
+ * base's other fields is seeded with `seed`; calib_values values per pool
+ * size are drawn with wn_fill_stats (in calls that fit `out`) and judged by
+ * wn_quality_check at z_max; each passing candidate then times the caller's
+ * request (streams, counts, out_dtype; one untimed call, three timed back to
+ * back on hip_stream).  *chosen receives base with the fastest passing (n, R):
+ * create the generator from it, so that its values follow from that stated
+ * configuration.  report[0 .. min(*nreport, report_cap)) receives every
+ * candidate measured.  Synchronous; allocates temporary generators.
+ * Errors: WN_EINVAL (arguments), WN_ENOTSUP (no candidate passed; *chosen
+ * unchanged), and any error of the calls it makes. */
+typedef struct {
+  uint32_t struct_size;     /* sizeof(wn_quality_tuning) */
+  uint32_t pool_sizes[8];   /* candidate pool sizes, 0-terminated (none: 1024, 2048, 4096) */
+  uint32_t passes[8];       /* candidate R, 0-terminated (none: 1, 2, 3) */
+  uint64_t calib_values;    /* values per candidate and pool size for the battery (0: 2^30) */
+  double z_max;             /* every statistic within z_max standard errors (0: 5) */
+} wn_quality_tuning;
+typedef struct {
+  uint32_t pool_n;          /* 0: the per-stream sizes of base */
+  uint32_t R;
+  uint32_t passed;          /* the battery passed for every pool size */
+  uint32_t failed_mask;     /* union of wn_quality.failed_mask */
+  double worst_z;           /* largest |z| (histogram and clustering one-sided) */
+  float ms;                 /* time of the caller's request (0 if the candidate failed) */
+  uint32_t reserved;
+} wn_tune_candidate;
+wn_status wn_tune_config(const wn_config *base, const wn_quality_tuning *opts, uint32_t nreq,
+                         const uint32_t *streams, const uint64_t *counts, void *out,
+                         wn_dtype out_dtype, uint64_t seed, void *hip_stream, wn_config *chosen,
+                         wn_tune_candidate *report, uint32_t report_cap, uint32_t *nreport);
+
 /* Wait for the generator's outstanding work and report a fault a kernel
  * flagged since the last check (a non-finite or zero sum of squares):
  * WN_EDEVICE with a message, else WN_OK. */

@@ -17,7 +17,8 @@ LAUNCH_UNITS = ("wn_launch_f32_f32.hip", "wn_launch_f32_bf16.hip", "wn_launch_f3
                 "wn_launch_f64_f64.hip", "wn_launch_f64_f32.hip", "wn_launch_f64_bf16.hip",
                 "wn_launch_f64_f16.hip")
 SOURCES = [os.path.join(CSRC, f) for f in
-           LAUNCH_UNITS + ("wn_stats.hip", "wn_noalloc.hip", "wn_bench.hip", "wn_api.cpp")]
+           LAUNCH_UNITS + ("wn_stats.hip", "wn_noalloc.hip", "wn_bench.hip", "wn_api.cpp",
+                             "wn_tune.cpp")]
 HEADERS = [os.path.join(CSRC, f) for f in ("wn_internal.hpp", "wn_device.hpp", "wn_launch.hpp")] + [
     os.path.join(ROOT, "include", "wn.h"), os.path.join(ROOT, "include", "wn_bench.h")]
 BUILD_DIR = os.path.join(ROOT, "_build")

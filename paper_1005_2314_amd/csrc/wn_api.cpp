@@ -23,15 +23,15 @@
 
 namespace {
 
-thread_local std::string g_last_error;
+// the calling thread's last message (a fixed buffer: reporting an error
+// allocates nothing)
+thread_local char g_last_error[512];
 
 wn_status fail(wn_status st, const char *fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  std::vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
   va_end(ap);
-  g_last_error = buf;
   return st;
 }
 
@@ -279,7 +279,7 @@ wn_status wn_chi2_constants(uint32_t n, double *out) {
   return WN_OK;
 }
 
-const char *wn_last_error(void) { return g_last_error.c_str(); }
+const char *wn_last_error(void) { return g_last_error; }
 
 wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   if (!out_gen) return fail(WN_EINVAL, "wn_create: out_gen is NULL");
@@ -1153,3 +1153,9 @@ wn_status wn_load_state(wn_gen *g, const void *host_buf, size_t bytes) {
 void wn_destroy(wn_gen *g) { release(g); }
 
 }  // extern "C"
+
+namespace wn {
+void set_last_error(const char *msg) {
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s", msg);
+}
+}  // namespace wn

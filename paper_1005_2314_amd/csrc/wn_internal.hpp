@@ -117,6 +117,9 @@ struct FillArgs {
   StatsOut *stats = nullptr;        // fused statistics: histogram and tails accumulate here
 };
 
+// The message wn_last_error() returns to the calling thread (wn_api.cpp).
+void set_last_error(const char *msg);
+
 // wn_fill_stats_noalloc: the statically allocated partials (wn_noalloc.hip).
 // noalloc_partials returns their device address on `device`, which must be the
 // current device; the first call on a device looks it up.

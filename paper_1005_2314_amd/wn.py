@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "WN_OK", 1: "WN_EINVAL", 2: "WN_ENOMEM", 3: "WN_EDEVICE", 4: 
 EXPORTED = ("wn_create", "wn_seed", "wn_fill", "wn_sync", "wn_get_stream", "wn_destroy",
             "wn_state_size", "wn_save_state", "wn_load_state",
             "wn_last_error", "wn_version", "wn_set_tuning", "wn_get_tuning", "wn_autotune",
-            "wn_fill_stats", "wn_fill_stats_noalloc", "wn_extreme_threshold", "wn_chi2_constants", "wn_bench_store",
+            "wn_fill_stats", "wn_fill_stats_noalloc", "wn_quality_check", "wn_tune_config",
+            "wn_extreme_threshold", "wn_chi2_constants", "wn_bench_store",
             "wn_bench_traffic",
             "wn_bench_box_muller")
 
@@ -65,6 +66,27 @@ class wn_stats(C.Structure):
                 ("t_sumsq", C.c_double), ("t_pairs", C.c_uint64), ("t_lag", C.c_double),
                 ("hist", C.c_uint64 * HIST_BINS), ("x_pools", C.c_uint64),
                 ("x_pairs", C.c_uint64)]
+
+
+WN_QUALITY_NAMES = ("mean", "var", "skew", "kurt", "hist", "pool_mean", "pool_var", "pool_lag",
+                    "extreme_pairs")
+WN_QUALITY_NZ = len(WN_QUALITY_NAMES)
+
+
+class wn_quality(C.Structure):
+    _fields_ = [("z", C.c_double * WN_QUALITY_NZ), ("passed", C.c_uint32),
+                ("failed_mask", C.c_uint32)]
+
+
+class wn_quality_tuning(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("pool_sizes", C.c_uint32 * 8),
+                ("passes", C.c_uint32 * 8), ("calib_values", C.c_uint64), ("z_max", C.c_double)]
+
+
+class wn_tune_candidate(C.Structure):
+    _fields_ = [("pool_n", C.c_uint32), ("R", C.c_uint32), ("passed", C.c_uint32),
+                ("failed_mask", C.c_uint32), ("worst_z", C.c_double), ("ms", C.c_float),
+                ("reserved", C.c_uint32)]
 
 
 class WnError(RuntimeError):
@@ -120,6 +142,15 @@ def load():
         L.wn_fill_stats.restype = C.c_int
         L.wn_fill_stats_noalloc.argtypes = L.wn_fill_stats.argtypes
         L.wn_fill_stats_noalloc.restype = C.c_int
+        L.wn_quality_check.argtypes = [C.POINTER(wn_stats), C.c_uint32, C.c_double,
+                                       C.POINTER(wn_quality)]
+        L.wn_quality_check.restype = C.c_int
+        L.wn_tune_config.argtypes = [C.POINTER(wn_config), C.POINTER(wn_quality_tuning),
+                                     C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
+                                     vp, C.c_int, C.c_uint64, vp, C.POINTER(wn_config),
+                                     C.POINTER(wn_tune_candidate), C.c_uint32,
+                                     C.POINTER(C.c_uint32)]
+        L.wn_tune_config.restype = C.c_int
         L.wn_extreme_threshold.argtypes = [C.c_uint32]
         L.wn_extreme_threshold.restype = C.c_double
         L.wn_chi2_constants.argtypes = [C.c_uint32, C.POINTER(C.c_double)]
@@ -236,6 +267,46 @@ def chi2_constants(n):
     out = (C.c_double * 6)()
     check(load().wn_chi2_constants(int(n), out))
     return tuple(out)
+
+
+def quality_check(stats, pool_n, z_max=5.0):
+    """wn_quality_check on a host wn_stats: (passed, {name: z}, failed_mask)."""
+    q = wn_quality()
+    check(load().wn_quality_check(C.byref(stats), int(pool_n), float(z_max), C.byref(q)))
+    return bool(q.passed), dict(zip(WN_QUALITY_NAMES, list(q.z))), int(q.failed_mask)
+
+
+def tune_config(cfg, out, streams, counts, seed=1, pool_sizes=(), passes=(), calib_values=0,
+                z_max=0.0, stream=None):
+    """wn_tune_config: the fastest (pool size, R) that passes the statistics
+    battery, for the request (streams, counts) into the CUDA tensor `out`.
+    Returns (chosen wn_config, list of wn_tune_candidate)."""
+    import torch
+    dt = {torch.float64: WN_F64, torch.float32: WN_F32, torch.bfloat16: WN_BF16,
+          torch.float16: WN_F16}[out.dtype]
+    o = wn_quality_tuning()
+    o.struct_size = C.sizeof(wn_quality_tuning)
+    for i, v in enumerate(pool_sizes):
+        o.pool_sizes[i] = int(v)
+    for i, v in enumerate(passes):
+        o.passes[i] = int(v)
+    o.calib_values = int(calib_values)
+    o.z_max = float(z_max)
+    streams = np.ascontiguousarray(streams, np.uint32)
+    counts = np.ascontiguousarray(counts, np.uint64)
+    chosen = wn_config()
+    rep = (wn_tune_candidate * 64)()
+    nrep = C.c_uint32()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    status = load().wn_tune_config(C.byref(cfg), C.byref(o), streams.size,
+                                   streams.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                   counts.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                   C.c_void_p(out.data_ptr()), dt, int(seed),
+                                   C.c_void_p(st.cuda_stream), C.byref(chosen), rep, 64,
+                                   C.byref(nrep))
+    report = [rep[i] for i in range(min(nrep.value, 64))]
+    check(status)
+    return chosen, report
 
 
 def torch_dtype(out_dtype):
