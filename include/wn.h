@@ -138,6 +138,11 @@ typedef struct {
                                   compute unit with pools of 1024 or 2048 values; bit 1: the
                                   items of 1024 and 2048 values of persistent launches whose
                                   pools are at most 4096.  0..3, default 1 */
+  uint32_t group_items;        /* persistent launches without statistics, thinning or rotations,
+                                  pools of at most 4096: 1 = the items of 1024 values outside the
+                                  long-item head run in pairs, one per half of the workgroup
+                                  (128 threads each), neighbours in length, in the plain loop
+                                  (same results); default 0 */
 } wn_tuning;
 
 /* Validate cfg, select the device, allocate the per-stream state in device
@@ -316,7 +321,8 @@ wn_status wn_get_stream(wn_gen *g, uint32_t s, wn_stream_info *info, void *pool_
 /* Set or read the generator's launch choices.  wn_set_tuning validates the
  * struct (WN_EINVAL on a bad size, a flag other than 0/1, waves_per_simd other
  * than 0/5/6/8 or set with nontemporal_stores, wgs_per_cu > 16,
- * long_priority_pct > 100, streams_per_wg outside 1..16 or defer_emission > 3)
+ * long_priority_pct > 100, streams_per_wg outside 1..16, defer_emission > 3 or
+ * group_items > 1)
  * and applies to later calls.  Binary32 pools of
  * 1024..8192 values have every choice; other shapes, and the plane-rotation
  * family (one launch variant), ignore them.  Defaults: the choices measured
@@ -326,7 +332,7 @@ wn_status wn_get_tuning(wn_gen *g, wn_tuning *t);
 
 /* Autotune the launch choices for one request shape.  A measurement of a
  * candidate (LDS buffering, store kind, streams per workgroup, deferred
- * emission; for persistent launches grid size and long-item priority) runs the
+ * emission; for persistent launches grid size, long-item priority and pairs) runs the
  * request once untimed and three times back to back, timed with HIP events on
  * hip_stream, then restores the generator's state.  Every candidate is measured
  * twice (the better counts), the three fastest five more times each in turn,

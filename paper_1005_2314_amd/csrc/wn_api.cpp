@@ -113,7 +113,7 @@ struct PersistentSlot {
   hipGraphExec_t exec = nullptr;
   // key of the cached graph
   uint32_t k_nitems = 0, k_dtype = 0, k_variant = 0, k_grid = 0, k_max_n = 0, k_prio = 0;
-  uint32_t k_defer = 0;
+  uint32_t k_defer = 0, k_entries = 0;
   void *k_out = nullptr;
 };
 
@@ -150,6 +150,7 @@ struct wn_gen {
   uint32_t long_priority_pct = 25;
   uint32_t streams_per_wg = 1;
   uint32_t defer_emission = 1;  // bit 0: one-size launches of few streams, bit 1: persistent
+  uint32_t group_items = 0;     // persistent launches: 1 = pairs of 1024-value items
   bool use_graph = true;
   uint32_t cus = 256;        // compute units of the device
   // persistent launches: two staging/work-list slots, each with a cached graph
@@ -533,13 +534,16 @@ hipError_t reserve(wn::WorkItem **host, wn::WorkItem **dev, size_t *cap, size_t 
 // first, to slot.host[0 .. nitems): replays the slot's graph when the launch
 // shape is unchanged, captures a new one otherwise (or launches directly when
 // graphs are off).
-hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, uint32_t prio_items,
-                             uint32_t max_n, void *out, uint32_t dtype, wn::StatsOut *stats,
-                             wn::StatsPartial *partials, hipStream_t st) {
+// With nentries > 0 the list is slot.host[0 .. nitems) followed by nentries
+// entry words (pairs of items, kEntry*), and the launch runs the entries.
+hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, uint32_t nentries,
+                             uint32_t prio_items, uint32_t max_n, void *out, uint32_t dtype,
+                             wn::StatsOut *stats, wn::StatsPartial *partials, hipStream_t st) {
   wn::FillArgs a;
   a.c = common(g, 0);
   a.items = slot.dev;
-  a.nitems = nitems;
+  a.nitems = nentries ? nentries : nitems;
+  a.entries = nentries ? reinterpret_cast<const uint32_t *>(slot.dev + nitems) : nullptr;
   a.affine_s0 = 0;
   a.count_each = 0;
   a.out = out;
@@ -554,7 +558,7 @@ hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, u
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   const uint32_t grid = g->wgs_per_cu ? uint32_t(cus) * g->wgs_per_cu : 0;
-  const size_t bytes = size_t(nitems) * sizeof(wn::WorkItem);
+  const size_t bytes = size_t(nitems) * sizeof(wn::WorkItem) + size_t(nentries) * sizeof(uint32_t);
   if (!g->use_graph || stats) {
     if ((e = hipMemcpyAsync(slot.dev, slot.host, bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
       return e;
@@ -562,7 +566,8 @@ hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, u
   }
   const bool hit = slot.exec && slot.k_nitems == nitems && slot.k_dtype == dtype &&
                    slot.k_variant == g->variant && slot.k_grid == grid && slot.k_max_n == max_n &&
-                   slot.k_out == out && slot.k_prio == prio_items && slot.k_defer == a.defer;
+                   slot.k_out == out && slot.k_prio == prio_items && slot.k_defer == a.defer &&
+                   slot.k_entries == nentries;
   if (!hit) {
     if (slot.exec) {
       (void)hipGraphExecDestroy(slot.exec);
@@ -592,6 +597,7 @@ hipError_t launch_persistent(wn_gen *g, PersistentSlot &slot, uint32_t nitems, u
     slot.k_out = out;
     slot.k_prio = prio_items;
     slot.k_defer = a.defer;
+    slot.k_entries = nentries;
   }
   return hipGraphLaunch(slot.exec, st);
 }
@@ -665,8 +671,18 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
         return hip_fail(e, "wn_fill: staging wait");
       slot.pending = false;
     }
+    // Items of 1024 values may share a workgroup in pairs, one per half of 128
+    // threads, in the plain loop (no statistics, thinning or rotations; pools
+    // of at most 4096 values).  With the deferred form on, the items that run
+    // alone take it.
+    const uint32_t group = (!stats && g->stride == 1 && g->transform == 0 && max_n <= 4096)
+                               ? g->group_items
+                               : 0u;
+    const size_t entry_slots = group ? (size_t(nbig) * sizeof(uint32_t) + sizeof(wn::WorkItem) - 1) /
+                                           sizeof(wn::WorkItem)
+                                     : 0;
     wn::WorkItem *old_dev = slot.dev;
-    if ((e = reserve(&slot.host, &slot.dev, &slot.cap, nbig)) != hipSuccess)
+    if ((e = reserve(&slot.host, &slot.dev, &slot.cap, nbig + entry_slots)) != hipSuccess)
       return hip_fail(e, "wn_fill: work list allocation");
     if (slot.dev != old_dev && slot.exec) {  // the cached graph points at the old list
       (void)hipGraphExecDestroy(slot.exec);
@@ -685,17 +701,67 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
     }
     std::stable_sort(order.begin(), order.end(),
                      [](const auto &x, const auto &y) { return x.first > y.first; });
-    for (uint32_t i = 0; i < nbig; ++i) {
-      const uint32_t j = order[i].second;
-      slot.host[i] = wn::WorkItem{streams[j], j, counts[j], off[j]};
+    uint32_t prio_items = 0, nentries = 0;
+    if (!group) {
+      for (uint32_t i = 0; i < nbig; ++i) {
+        const uint32_t j = order[i].second;
+        slot.host[i] = wn::WorkItem{streams[j], j, counts[j], off[j]};
+      }
+      if (g->long_priority_pct > 0) {
+        const uint64_t cut = order[0].first * g->long_priority_pct / 100;
+        while (prio_items < nbig && order[prio_items].first >= cut) ++prio_items;
+      }
+    } else {
+      // Pairs of 1024-value items, neighbours in length (the list is longest
+      // first).  The long items (estimated work at least long_priority_pct of
+      // the longest, 25 when that is 0) run alone, as the critical path; a
+      // pair's half has twice the values per thread, so its step costs about
+      // what a pool of twice the size costs alone.  Entries are ordered
+      // longest first; the long ones run at raised priority.
+      const uint32_t pct = g->long_priority_pct ? g->long_priority_pct : 25u;
+      const uint64_t cut = order[0].first * pct / 100;
+      const uint32_t per = 2u;
+      struct Entry {
+        uint64_t est;
+        uint32_t first, k;  // k requests from members[first]
+      };
+      std::vector<Entry> ent;
+      std::vector<uint32_t> members;
+      ent.reserve(nbig);
+      members.reserve(nbig);
+      std::vector<std::pair<uint64_t, uint32_t>> small;  // (pools, request), longest first
+      for (uint32_t i = 0; i < nbig; ++i) {
+        const uint32_t j = order[i].second;
+        const uint32_t n = g->pool_n[streams[j]];
+        if (n != 1024 || order[i].first >= cut) {
+          ent.push_back(Entry{order[i].first, uint32_t(members.size()), 1});
+          members.push_back(j);
+        } else {
+          small.emplace_back(order[i].first / (n + 4096), j);
+        }
+      }
+      for (size_t i = 0; i < small.size(); i += per) {
+        const uint32_t k = uint32_t(std::min<size_t>(per, small.size() - i));
+        const uint64_t cost = k == 1 ? 1024 + 4096 : per * 1024 + 4096;
+        ent.push_back(Entry{small[i].first * cost, uint32_t(members.size()), k});
+        for (uint32_t m = 0; m < k; ++m) members.push_back(small[i + m].second);
+      }
+      std::stable_sort(ent.begin(), ent.end(),
+                       [](const Entry &x, const Entry &y) { return x.est > y.est; });
+      auto *words = reinterpret_cast<uint32_t *>(slot.host + nbig);
+      uint32_t k = 0;
+      for (const Entry &en : ent) {
+        const uint32_t kind = en.k == 2 ? wn::kEntryPair : wn::kEntrySolo;
+        words[nentries++] = k | (kind << wn::kEntryKindShift);
+        for (uint32_t m = 0; m < en.k; ++m) {
+          const uint32_t j = members[en.first + m];
+          slot.host[k++] = wn::WorkItem{streams[j], j, counts[j], off[j]};
+        }
+        if (en.est >= cut) ++prio_items;
+      }
     }
-    uint32_t prio_items = 0;
-    if (g->long_priority_pct > 0) {
-      const uint64_t cut = order[0].first * g->long_priority_pct / 100;
-      while (prio_items < nbig && order[prio_items].first >= cut) ++prio_items;
-    }
-    if ((e = launch_persistent(g, slot, nbig, prio_items, max_n, out, uint32_t(out_dtype), stats,
-                               partials, st)) != hipSuccess)
+    if ((e = launch_persistent(g, slot, nbig, nentries, prio_items, max_n, out,
+                               uint32_t(out_dtype), stats, partials, st)) != hipSuccess)
       return hip_fail(e, "wn_fill: persistent launch");
     if ((e = hipEventRecord(slot.done, st)) != hipSuccess) return hip_fail(e, "wn_fill: event");
     slot.pending = true;
@@ -914,7 +980,8 @@ wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t) {
   const uint32_t wcode = w == 0 ? 0u : w == 8 ? 1u : w == 6 ? 2u : w == 5 ? 3u : 4u;
   if (t->lds_double_buffer > 1 || t->nontemporal_stores > 1 || wcode > 3 || t->use_graph > 1 ||
       (wcode && t->nontemporal_stores) || t->wgs_per_cu > 16 || t->long_priority_pct > 100 ||
-      t->streams_per_wg < 1 || t->streams_per_wg > 16 || t->defer_emission > 3)
+      t->streams_per_wg < 1 || t->streams_per_wg > 16 || t->defer_emission > 3 ||
+      t->group_items > 1)
     return fail(WN_EINVAL, "wn_set_tuning: flags must be 0 or 1, waves_per_simd 0/5/6/8 and "
                            "not with nontemporal_stores, wgs_per_cu <= 16, "
                            "long_priority_pct <= 100, streams_per_wg in [1, 16], "
@@ -925,6 +992,7 @@ wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t) {
   g->long_priority_pct = t->long_priority_pct;
   g->streams_per_wg = t->streams_per_wg;
   g->defer_emission = t->defer_emission;
+  g->group_items = t->group_items;
   return WN_OK;
 }
 
@@ -940,6 +1008,7 @@ wn_status wn_get_tuning(wn_gen *g, wn_tuning *t) {
   t->long_priority_pct = g->long_priority_pct;
   t->streams_per_wg = g->streams_per_wg;
   t->defer_emission = g->defer_emission;
+  t->group_items = g->group_items;
   return WN_OK;
 }
 
@@ -967,8 +1036,9 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
              g->pool_n[streams[j]] == g->pool_n[streams[0]];
   std::vector<wn_tuning> cands;
   auto add = [&](uint32_t db, uint32_t nt, uint32_t oc, uint32_t wpc, uint32_t prio,
-                 uint32_t spw = 1, uint32_t defer = 0) {
+                 uint32_t spw = 1, uint32_t defer = 0, uint32_t group = 0) {
     wn_tuning t = cur;
+    t.group_items = group;
     t.defer_emission = defer;
     t.streams_per_wg = spw;
     t.lds_double_buffer = db;
@@ -989,12 +1059,15 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
     add(1, 1, 0, cur.wgs_per_cu, cur.long_priority_pct, 1, keep_defer & 2u);
     if (nreq <= g->cus) add(1, 0, 0, cur.wgs_per_cu, cur.long_priority_pct, 1, keep_defer | 1u);
   } else {
-    for (uint32_t prio : {0u, 10u, 25u})
-      for (uint32_t db = 0; db < 2; ++db)
-        for (uint32_t wpc : {0u, 3u, 4u, 6u}) add(db, 0, 0, wpc, prio, 1, keep_defer & 1u);
+    for (uint32_t group = 0; group < 2; ++group)
+      for (uint32_t prio : {0u, 10u, 25u})
+        for (uint32_t db = 0; db < 2; ++db)
+          for (uint32_t wpc : {0u, 3u, 4u, 6u})
+            add(db, 0, 0, wpc, prio, 1, keep_defer & 1u, group);
     add(1, 1, 0, 0, 25, 1, keep_defer & 1u);
-    for (uint32_t prio : {0u, 25u})
-      for (uint32_t wpc : {0u, 2u, 3u}) add(1, 0, 0, wpc, prio, 1, keep_defer | 2u);
+    for (uint32_t group = 0; group < 2; ++group)
+      for (uint32_t prio : {0u, 25u, 50u})
+        for (uint32_t wpc : {0u, 2u, 3u, 4u}) add(1, 0, 0, wpc, prio, 1, keep_defer | 2u, group);
   }
 
   // snapshot of the state, restored after every candidate

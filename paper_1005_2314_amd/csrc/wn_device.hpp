@@ -370,11 +370,12 @@ struct StatsAcc {
 //   pool buffer(s)              n * sizeof(T), twice with two buffers
 //   sum-of-squares scratch      4 waves x min(NQ, 4) x 64 binary64 (NQ > 1 only)
 //   partial-sum slots           two sets of 4 * NQ binary64, used alternately
-//   2 words for broadcasts
+//   4 words for broadcasts (0: seeding; 1, 2: the pair form's pool counts;
+//     3: spare, the persistent kernel's item word when it is the last)
 //   with statistics: 16 slots, 4 flag words and the histogram.
 // Every part grows with n, so a persistent launch sized for its largest pool
 // holds every smaller pool's layout below its own last 8 bytes.
-constexpr size_t kMiscLds = 2 * sizeof(uint64_t);
+constexpr size_t kMiscLds = 4 * sizeof(uint64_t);
 
 __host__ __device__ constexpr uint32_t nq_of(uint32_t n) { return n >= 1024 ? n / 1024 : 1u; }
 // columns per thread handled in one round of the sum-of-squares transposition
@@ -411,20 +412,30 @@ __host__ __device__ constexpr size_t lds_bytes_for(uint32_t n, bool db, bool sta
 // writes before it.  Successive sumsq() calls use the two slot sets in turn,
 // so the next call's slot writes never meet this call's slot reads (every
 // wave has read them before it reaches the next call's barrier).
-template <typename T, int NQ, bool SMALL, bool DB>
+// BD: threads per item: 256 (one item per workgroup) or 128 (two items per
+// workgroup, one per half: the pair form of persistent launches).  The layout
+// and the results are the same for both: element i = m*L + c*BD + tid, with
+// NQ = L/BD.
+template <typename T, int NQ, bool SMALL, bool DB, int BD = int(kBlock)>
 struct Engine {
-  static constexpr uint32_t kSet = 4 * NQ;  // partial-sum slots per set
+  static_assert(BD == 256 || BD == 128, "items of 256 or 128 threads");
+  static constexpr uint32_t kWaves = uint32_t(BD) / 64;  // waves per item
+  static constexpr uint32_t kSet = kWaves * NQ;           // partial-sum slots per set
   T *base;      // LDS: pool buffer 0, then buffer 1 when DB
   double *red;  // LDS: two sets of kSet partial-sum slots
-  double *sqs;  // LDS: the sum-of-squares transposition scratch (NQ > 1)
-  uint32_t Lr;  // row length for SMALL pools (else the compile-time kBlock * NQ)
-  uint32_t tid;
+  double *sqs;  // LDS: the sum-of-squares transposition scratch of this item's waves (NQ > 1)
+  uint32_t Lr;  // row length for SMALL pools (else the compile-time BD * NQ)
+  uint32_t tid; // thread index within the item
   uint32_t cb;  // buffer holding the pool (0, or 1 when DB)
   uint32_t rs;  // slot set of the next sumsq() (0 or 1)
+  uint32_t lbase;  // LDS address of base (0, or a half's pool area in the pair form)
   T y[NQ][4];   // y[c][m] = element m*L + c*BD + tid
 
-  __device__ __forceinline__ uint32_t len() const { return SMALL ? Lr : kBlock * NQ; }
-  __device__ __forceinline__ uint32_t bd() const { return SMALL ? Lr : kBlock; }
+  // The item's threads meet (both halves of a pair take every barrier).
+  __device__ __forceinline__ static void sync() { __syncthreads(); }
+
+  __device__ __forceinline__ uint32_t len() const { return SMALL ? Lr : uint32_t(BD) * NQ; }
+  __device__ __forceinline__ uint32_t bd() const { return SMALL ? Lr : uint32_t(BD); }
   __device__ __forceinline__ uint32_t pool_n() const { return 4 * len(); }
 
   __device__ __forceinline__ uint32_t pos(int m, int c) const {
@@ -441,7 +452,7 @@ struct Engine {
   // address is a constant: the gather needs no address add per access.
   using LdsT = __attribute__((address_space(3))) const T;
   __device__ __forceinline__ LdsT *lds_buf(uint32_t b) const {
-    return reinterpret_cast<LdsT *>(uintptr_t(b * pool_n() * uint32_t(sizeof(T))));
+    return reinterpret_cast<LdsT *>(uintptr_t(lbase + b * pool_n() * uint32_t(sizeof(T))));
   }
   __device__ __forceinline__ T *cur() const { return DB ? buf(cb) : base; }
 
@@ -575,7 +586,7 @@ struct Engine {
         default: gather_transform<3, RB>(p, renorm, g); break;
       }
     }
-    if (!DB) __syncthreads();
+    if (!DB) sync();
     T *W = buf(WB);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -692,7 +703,7 @@ struct Engine {
         quad<0>(a, b, cc, d, y[c]);
       }
     }
-    if (!DB) __syncthreads();
+    if (!DB) sync();
     T *W = buf(WB);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -740,12 +751,12 @@ struct Engine {
   //   NQ = 1 (and SMALL): one column per thread; the tree over the threads
   //   is the tree over the columns.
   //   NQ > 1: the tree's nodes of 64 columns are the blocks (c, wave)
-  //   = columns c*256 + 64w .. +63.  Each wave writes its column sums to its
+  //   = columns c*BD + 64w .. +63.  Each wave writes its column sums to its
   //   own LDS scratch and reads them back transposed: lane l takes NQ
   //   consecutive columns of block (c, w), c = l / G, G = 64 / NQ, and sums
   //   them in-lane; a DPP tree over each group of G lanes gives the block's
-  //   node.  The 4 NQ nodes go to LDS slots in column order (c major, wave
-  //   minor), and every thread finishes the tree over them.
+  //   node.  The (BD/64) NQ nodes go to LDS slots in column order (c major,
+  //   wave minor), and every thread finishes the tree over them.
   // Ends with a barrier; every thread returns the same value.
   __device__ __forceinline__ double sumsq() {
     double col[NQ];
@@ -783,18 +794,26 @@ struct Engine {
       }
       if constexpr (G <= 16) {
         node = group_pairwise_sum<G>(node);
-        if (gl == 0) slots[cl * 4 + w] = node;
+        if (gl == 0) slots[cl * kWaves + w] = node;
       } else {  // NQ = 2: blocks of 32 lanes, rows of 16 combined by lane reads
         node = group_pairwise_sum<16>(node);
         const double b0 = __dadd_rn(readlane_f64(node, 0), readlane_f64(node, 16));
         const double b1 = __dadd_rn(readlane_f64(node, 32), readlane_f64(node, 48));
-        if (lane < 2) slots[lane * 4 + w] = lane == 0 ? b0 : b1;
+        if (lane < 2) slots[lane * kWaves + w] = lane == 0 ? b0 : b1;
       }
       __syncthreads();
-      double s[4 * NQ];
-#pragma unroll
-      for (int i = 0; i < 4 * NQ; ++i) s[i] = slots[i];
-      return pairwise<4 * NQ>(s);
+      // the tree over the kSet nodes: lane i of each wave takes node i, a DPP
+      // tree over the first kSet lanes, lane 0's result to every thread
+      const double v = lane < kSet ? slots[lane] : 0.0;
+      if constexpr (kSet <= 16) {
+        return readlane_f64(group_pairwise_sum<int(kSet)>(v), 0);
+      } else if constexpr (kSet == 32) {
+        const double r = group_pairwise_sum<16>(v);
+        return __dadd_rn(readlane_f64(r, 0), readlane_f64(r, 16));
+      } else {
+        static_assert(kSet == 64, "4, 8, 16, 32 or 64 nodes");
+        return wave_pairwise_sum(v);
+      }
     }
   }
 
@@ -927,6 +946,28 @@ __device__ __forceinline__ Engine<T, NQ, SMALL, DB> make_engine(unsigned char *s
   e.tid = threadIdx.x;
   e.cb = 0;
   e.rs = 0;
+  e.lbase = 0;
+  return e;
+}
+
+// The engine of half h (threads 128h .. 128h+127) of a workgroup whose LDS
+// is laid out for pools of nmax values (the pair form): pool buffer(s) in the
+// h-th half of the pool area (n <= nmax / 2), the transposition scratch of its
+// two waves and half of the slot area.  Both halves fit in the layout of one
+// pool of nmax values.
+template <typename T, int NQ, bool DB>
+__device__ __forceinline__ Engine<T, NQ, false, DB, 128> make_half_engine(unsigned char *smem,
+                                                                          uint32_t n, uint32_t nmax,
+                                                                          uint32_t h) {
+  Engine<T, NQ, false, DB, 128> e;
+  e.lbase = h * uint32_t(pool_lds<T>(nmax, DB) / 2);
+  e.base = reinterpret_cast<T *>(smem + e.lbase);
+  e.sqs = reinterpret_cast<double *>(smem + pool_lds<T>(nmax, DB) + h * (sq_scratch_lds(nmax) / 2));
+  e.red = reinterpret_cast<double *>(smem + slots_off<T>(nmax, DB)) + h * slot_set(nmax);
+  e.Lr = n / 4;
+  e.tid = threadIdx.x & 127u;
+  e.cb = 0;
+  e.rs = 0;
   return e;
 }
 
@@ -945,7 +986,7 @@ __device__ __forceinline__ void flag_fault(uint32_t *err, double Q) {
 }
 
 // ---- LDS regions after the partial-sum slots (offsets from misc_off) ----------------
-// broadcast word w (0 or 1)
+// broadcast word w (0 .. 3)
 __device__ __forceinline__ uint64_t *misc_word(unsigned char *smem, size_t misc, int w) {
   return reinterpret_cast<uint64_t *>(smem + misc) + w;
 }
@@ -1054,14 +1095,25 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
 // emission run inside the next pool's first pass (pass_finish), where the
 // binary64 chain of the scale overlaps the pass's LDS and ALU latency; the
 // last pool is finished after the loop.  Same values, same order of stores.
+//
+// PAIR: the item is half of a pair (128 threads, make_half_engine) and runs
+// the plain loop; nmax is the pool size the LDS is laid out for.
 template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, bool STATS, bool ROT,
-          bool DEFER = false>
+          bool DEFER = false, bool PAIR = false>
 __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem, uint32_t s,
-                                          uint64_t count, uint64_t obase, uint32_t req = 0) {
+                                          uint64_t count, uint64_t obase, uint32_t req = 0,
+                                          uint32_t nmax = 0) {
   static_assert(!(DEFER && STATS), "the deferred form carries no statistics");
+  static_assert(!(PAIR && (STATS || DEFER || SMALL)), "the pair form is the plain loop");
   StreamHdr *h = a.c.hdr + s;
   const uint32_t n = h->n;
-  auto e = make_engine<T, NQ, SMALL, DB>(smem, n);
+  const uint32_t half = threadIdx.x >> 7;
+  auto e = [&]() {
+    if constexpr (PAIR)
+      return make_half_engine<T, NQ, DB>(smem, n, nmax, half);
+    else
+      return make_engine<T, NQ, SMALL, DB>(smem, n);
+  }();
   StatsAcc sa;
   double t_sum = 0.0, t_sumsq = 0.0, t_lag = 0.0, tprev = 0.0;
   uint64_t pools = 0, t_pairs = 0, x_pools = 0, x_pairs = 0;
@@ -1088,7 +1140,22 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   O *out = reinterpret_cast<O *>(a.out);
 
   e.load_global(gpool);
-  __syncthreads();
+  // The pair form: both halves run the same number of pool steps (the larger
+  // of their pool counts), a half whose item is done taking only the steps'
+  // barriers.  Each half publishes its count across the barrier below.
+  uint64_t steps = 0;
+  if constexpr (PAIR) {  // (the pair form runs without thinning)
+    const uint64_t head = cursor < n - 1 ? take_of(count, n - 1 - cursor) : 0u;
+    const uint64_t rest = count - head;
+    const uint64_t mine = rest == 0 ? 0 : (rest - 1) / (n - 1) + 1;
+    if (e.tid == 0) *misc_word(smem, misc_off<T>(nmax, DB), 1 + int(half)) = mine;
+  }
+  e.sync();
+  if constexpr (PAIR) {
+    const uint64_t c0 = *misc_word(smem, misc_off<T>(nmax, DB), 1);
+    const uint64_t c1 = *misc_word(smem, misc_off<T>(nmax, DB), 2);
+    steps = c0 > c1 ? c0 : c1;
+  }
 
   // Options as wave-uniform scalars, so that each costs one scalar branch
   // per pool rather than vector selects (the defaults skip their work).
@@ -1185,7 +1252,7 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
           } else {
             e.template pass<ROT>(p, renorm && r == 0, g);
           }
-          if (r + 1 < R) __syncthreads();
+          if (r + 1 < R) e.sync();
         }
         pq = e.sumsq();
         plast = double(e.last());
@@ -1209,7 +1276,13 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
       if (bad && e.tid == 0) atomicOr(a.c.err, 1u);
     }
   }
-  while (!deferred && count > 0) {
+  for (uint64_t step = 0; !deferred && (PAIR ? step < steps : count > 0); ++step) {
+    if (PAIR && count == 0) {
+      // this half's item is done: the barriers of one pool step (2 per pass
+      // with one LDS buffer, 1 with two; the last one is the sum of squares')
+      for (uint32_t b = 0; b < (DB ? 1u : 2u) * a.c.R; ++b) __syncthreads();
+      continue;
+    }
     const bool renorm = k > 0 && K > 0 && k_mod == 0;
     double g = 1.0;
     if (renorm) g = __dsqrt_rn(__ddiv_rn(nd, qlast));
@@ -1222,7 +1295,7 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
       const uint64_t u1 = xs_next(xs);
       const uint64_t u2 = xs_next(xs);
       e.template pass<ROT>(decode_for<ROT>(u1, u2, e.len()), renorm && r == 0, g);
-      if (r + 1 < a.c.R) __syncthreads();
+      if (r + 1 < a.c.R) e.sync();
     }
     const double Q = e.sumsq();
     const double last = double(e.last());
@@ -1393,9 +1466,18 @@ __device__ __forceinline__ void item_as(const FillArgs &a, unsigned char *smem, 
 // 1024 .. 1024*MAXNQ, mixed) from a device counter in the order of the list
 // (the host sorts it longest first).  Every workgroup leaves the loop once the
 // counter passes the end of the list.
+// PAIRS: the list holds entries (a.entries): an item index and a kind
+// (kEntry*): one item run by the whole workgroup, or a pair, items i and i+1
+// of pool size 1024, run by the two halves at once (128 threads each) in the
+// plain loop; with DEFER the items that run alone take the deferred form as
+// usual.  (A pair of 2048-value pools would need 136 registers in this
+// layout, more than four waves per SIMD allow.)
+// With PAIRS the kernel is held to 128 registers (four waves per SIMD, so
+// eight streams per compute unit in pairs); combining the two paths would
+// otherwise take 143.
 template <typename T, typename O, int MAXNQ, bool DB, bool NT, bool STATS, bool ROT,
-          bool DEFER = false>
-__global__ __launch_bounds__(kBlock) void k_fill_persistent(FillArgs a) {
+          bool DEFER = false, bool PAIRS = false>
+__global__ __launch_bounds__(kBlock, PAIRS ? 4 : 1) void k_fill_persistent(FillArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   // the last 8 bytes of the allocation: the largest pool's spare broadcast
   // word (or the histogram's padding); no item's layout reaches them
@@ -1413,7 +1495,20 @@ __global__ __launch_bounds__(kBlock) void k_fill_persistent(FillArgs a) {
       __builtin_amdgcn_s_setprio(3);
     else
       __builtin_amdgcn_s_setprio(0);
-    const WorkItem it = a.items[j];
+    uint32_t idx = j;
+    if constexpr (PAIRS) {
+      static_assert(!STATS && MAXNQ == 4, "groups: no statistics, pools up to 4096");
+      const uint32_t v = a.entries[j];
+      idx = v & kEntryIndex;
+      const uint32_t kind = v >> kEntryKindShift;
+      if (kind == kEntryPair) {
+        const WorkItem it = a.items[idx + (threadIdx.x >> 7)];
+        fill_item<T, O, 2, false, DB, NT, false, ROT, false, true>(
+            a, smem, it.stream, it.count, it.out_off, it.req, 1024 * MAXNQ);
+        continue;
+      }
+    }
+    const WorkItem it = a.items[idx];
     if (it.count == 0) {
       if constexpr (STATS)
         if (threadIdx.x == 0) a.partials[it.req] = StatsPartial{};

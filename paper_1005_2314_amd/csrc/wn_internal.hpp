@@ -101,6 +101,13 @@ struct SeedArgs {
   uint64_t seed;
 };
 
+// Entry words of a persistent launch with pairs of items: the item index in
+// the low 28 bits, the kind above: one item per workgroup, or a pair (items i,
+// i+1, one per half of 128 threads).
+constexpr uint32_t kEntryKindShift = 28;
+constexpr uint32_t kEntryIndex = (1u << kEntryKindShift) - 1;
+constexpr uint32_t kEntrySolo = 0, kEntryPair = 1;
+
 struct FillArgs {
   KernelCommon c;
   const WorkItem *items = nullptr;  // device array, or null for the affine form below
@@ -111,6 +118,7 @@ struct FillArgs {
   void *out = nullptr;
   uint32_t variant = 0;             // non-semantic kernel variant (wn_tuning)
   uint32_t *counter = nullptr;      // persistent form: next work item (reset by the launch)
+  const uint32_t *entries = nullptr; // persistent form with groups: entry words (kEntry*)
   uint32_t prio_items = 0;          // persistent form: items [0, prio_items) run at priority 3
   uint32_t defer = 0;               // 1: the deferred form where it applies (latency-bound)
   StatsPartial *partials = nullptr; // fused statistics: one partial per request, or null

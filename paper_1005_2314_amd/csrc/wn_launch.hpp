@@ -150,10 +150,10 @@ hipError_t fill_n(const FillArgs &a, hipStream_t st) {
 // can be resident); resets a.counter first (a kernel, not a memset, so that
 // the two launches can be captured in a graph).
 template <typename T, typename O, int MAXNQ, bool DB, bool NT, bool STATS = false,
-          bool ROT = false, bool DEFER = false>
+          bool ROT = false, bool DEFER = false, bool PAIRS = false>
 hipError_t persistent_t(const FillArgs &a, uint32_t grid, hipStream_t st) {
   const size_t lds = lds_bytes_for<T>(1024u * MAXNQ, DB, STATS);
-  auto kern = k_fill_persistent<T, O, MAXNQ, DB, NT, STATS, ROT, DEFER>;
+  auto kern = k_fill_persistent<T, O, MAXNQ, DB, NT, STATS, ROT, DEFER, PAIRS>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
   if (grid == 0) {  // as many workgroups as can be resident at once
@@ -206,6 +206,15 @@ hipError_t persistent_v(const FillArgs &a, uint32_t grid, hipStream_t st) {
 template <typename T, typename O>
 hipError_t persistent_n(const FillArgs &a, uint32_t max_n, uint32_t grid, hipStream_t st) {
   if (a.nitems == 0) return hipSuccess;
+  if (a.entries) {  // pairs of small-pool items (plain loop, A4 passes, pools up to 4096)
+    if (a.partials || a.c.transform || a.c.stride != 1 || max_n > 4096)
+      return hipErrorInvalidValue;
+    if (a.defer)  // the items that run alone take the deferred form (two LDS buffers)
+      return persistent_t<T, O, 4, true, false, false, false, true, true>(a, grid, st);
+    if (a.variant & 1u)
+      return persistent_t<T, O, 4, true, false, false, false, false, true>(a, grid, st);
+    return persistent_t<T, O, 4, false, false, false, false, false, true>(a, grid, st);
+  }
   if (defer_applies(a, max_n, 4096))  // two LDS buffers of the largest pool fit for both types
     return a.c.transform ? persistent_t<T, O, 4, true, false, false, true, true>(a, grid, st)
                          : persistent_t<T, O, 4, true, false, false, false, true>(a, grid, st);

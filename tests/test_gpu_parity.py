@@ -231,6 +231,23 @@ def test_persistent_launch_shapes_bit_exact(use_graph, wgs, prio):
     assert_bits_equal(g, o, "new shape")
 
 
+@pytest.mark.parametrize("db,defer,prio", [(0, 1, 25), (1, 1, 0), (0, 3, 50), (1, 1, 100)])
+def test_persistent_pairs_bit_exact(db, defer, prio):
+    # pairs of 1024-value items, one per half of the workgroup (128 threads
+    # each, the same results as 256): lengths that end at different pools, so
+    # one half idles through the barriers of the other's remaining pools
+    sizes = np.array([1024] * 12 + [2048, 4096, 4096], np.uint32)
+    p = Pair(len(sizes), pool_n=sizes, R=2, seed=23)
+    p.gpu.set_tuning(group_items=1, lds_double_buffer=db, defer_emission=defer,
+                     long_priority_pct=prio)
+    rng = np.random.default_rng(prio)
+    for call in range(3):
+        order, counts = _request(rng, len(sizes), 30000)
+        counts[rng.integers(0, len(sizes))] = 0
+        g, o = p.fill(order, counts, W.WN_F32 if call != 1 else W.WN_F16)
+        assert_bits_equal(g, o, f"pairs, call {call}")
+
+
 def test_persistent_with_small_pools_mixed_in():
     sizes = np.array([64, 1024, 256, 4096, 16, 2048, 16384, 512], np.uint32)
     p = Pair(len(sizes), pool_n=sizes, R=2, seed=2)
