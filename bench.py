@@ -31,6 +31,8 @@ def parse():
                     help="wall time of the timed oracle baseline calls")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the other workload configurations")
     return ap.parse_args()
 
 
@@ -145,7 +147,7 @@ def time_launch(fn, stream, reps=3, warmup=1):
 
 
 def comparators(W, w, out, stream):
-    """Reference points on the same GPU: HBM write ceiling, the generator's traffic
+    """Reference points on the same GPU: HBM write ceilings, the generator's traffic
     with no arithmetic, the plain single-stream binary64 form, Box-Muller."""
     import ctypes as C
 
@@ -156,9 +158,10 @@ def comparators(W, w, out, stream):
     total = out.numel()
     st = C.c_void_p(stream.cuda_stream)
     optr = C.c_void_p(out.data_ptr())
-    for width in (1, 4):
-        ms = time_launch(lambda: W.wn_bench_store(optr, total * 4, width, st), stream)
-        res[f"store_ceiling_dwordx{width}"] = {"ms": ms, "GB_per_s": total * 4 / ms / 1e6}
+    for name, code in (("store_ceiling_dwordx1", 1), ("store_ceiling_dwordx4", 4),
+                       ("store_ceiling_runs_256KiB", 1 | 0x200)):
+        ms = time_launch(lambda: W.wn_bench_store(optr, total * 4, code, st), stream)
+        res[name] = {"ms": ms, "GB_per_s": total * 4 / ms / 1e6}
     n = w["pool_n"]
     state = torch.zeros(w["num_streams"] * (n * 4 + 64), dtype=torch.uint8, device=out.device)
     sptr = C.c_void_p(state.data_ptr())
@@ -167,7 +170,8 @@ def comparators(W, w, out, stream):
     out_b, state_b = workload_bytes(w, 4)
     res["traffic_ceiling"] = {"ms": ms, "GB_per_s": (out_b + state_b) / ms / 1e6,
                               "normals_per_s": total / ms * 1e3,
-                              "what": "the fill's HBM traffic with no arithmetic"}
+                              "what": "a plain streaming copy of the fill's bytes (pools and "
+                                      "headers read and written, outputs written), no arithmetic"}
     del state
     for fast in (0, 1):
         ms = time_launch(lambda: W.wn_bench_box_muller(optr, total, W.WN_F32, 1, fast, st), stream)
@@ -181,6 +185,109 @@ def comparators(W, w, out, stream):
     res["plain_f64_single_stream"] = {"ms": ms, "normals_per_s": o64.numel() / ms * 1e3,
                                       "what": "1 stream, pool 1024 binary64, R=1, 2^20 binary64"}
     g.close()
+    return res
+
+
+def other_workloads(W, stream):
+    """The other workload configurations, each timed in the launch form it runs in
+    (steady state: untimed calls first, then the mean of back-to-back calls)."""
+    import numpy as np
+    import torch
+
+    from paper_1005_2314_amd import inputs
+    res = {}
+
+    def steady(fn, reps=3):
+        """Mean duration (ms) of `reps` calls back to back, after untimed calls
+        that keep the GPU busy for about 50 ms (clocks settle after an idle
+        host phase)."""
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        fn()
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        for _ in range(min(200, int(50.0 / max(a.elapsed_time(b), 0.05)))):
+            fn()
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    # plain single-stream binary64 form (one pool-1024 stream, one pass per pool)
+    p = inputs.plain_f64()
+    g = W.Generator(1, pool_n=p["pool_n"], R=p["R"], pool_dtype=W.WN_F64)
+    g.seed(p["seed"])
+    o = torch.empty(int(p["counts"][0]), dtype=torch.float64, device="cuda")
+    ms = steady(lambda: g.fill_into(o, p["streams"], p["counts"], stream))
+    res["plain_f64"] = {"config": "1 stream, pool 1024 binary64, R=1, 2^20 binary64 out",
+                        "ms": ms, "normals_per_s": o.numel() / ms * 1e3}
+    g.close()
+    del o
+
+    # uneven batch: one persistent launch replayed from a HIP graph; R from the
+    # quality-constrained tuner (candidates 1, 2, 3 at 2^30 calibration values per
+    # pool size), then the launch choices by the autotuner
+    u = inputs.uneven()
+    total = int(u["counts"].sum())
+    o = torch.empty(total, dtype=torch.float32, device="cuda")
+    base, keep = W.make_config(u["num_streams"], u["pool_n"], R=u["R"])
+    chosen, report = W.tune_config(base, o, u["streams"], u["counts"], seed=u["seed"],
+                                   passes=(1, 2, 3))
+    R = chosen.passes_per_output
+    entry = {"config": "10000 streams, log-uniform counts in [2^10, 2^22), pools 1024/2048/4096 "
+                       "binary32, one persistent graph-replayed launch",
+             "total_normals": total, "passes_chosen": R,
+             "candidates": [{"R": c.R, "passed": bool(c.passed), "worst_z": c.worst_z,
+                             "ms": c.ms} for c in report]}
+    for r in sorted({R, 2}):
+        g = W.Generator(u["num_streams"], pool_n=u["pool_n"], R=r)
+        g.seed(u["seed"])
+        t = g.autotune(o, u["streams"], u["counts"], stream)
+        ms = steady(lambda: g.fill_into(o, u["streams"], u["counts"], stream))
+        entry[f"R{r}"] = {"ms": ms, "normals_per_s": total / ms * 1e3,
+                          "tuning": {"wgs_per_cu": t.wgs_per_cu, "group_items": t.group_items,
+                                     "lds_double_buffer": t.lds_double_buffer,
+                                     "long_priority_pct": t.long_priority_pct,
+                                     "defer_emission": t.defer_emission}}
+        g.close()
+    entry["ms"] = entry[f"R{R}"]["ms"]
+    entry["normals_per_s"] = entry[f"R{R}"]["normals_per_s"]
+    res["uneven"] = entry
+    del o, keep
+
+    # precision workload: binary32 pools, 16-bit outputs
+    q = inputs.precision()
+    g = W.Generator(q["num_streams"], pool_n=q["pool_n"], R=q["R"])
+    g.seed(q["seed"])
+    entry = {"config": "16384 streams x 2^16, pool 4096 binary32, R=2"}
+    for dt, name in ((W.WN_BF16, "bf16"), (W.WN_F16, "f16"), (W.WN_F32, "f32")):
+        o = torch.empty(int(q["counts"].sum()), dtype=W.torch_dtype(dt), device="cuda")
+        ms = steady(lambda: g.fill_into(o, q["streams"], q["counts"], stream))
+        entry[f"{name}_out"] = {"ms": ms, "normals_per_s": o.numel() / ms * 1e3}
+        del o
+    res["precision"] = entry
+    g.close()
+
+    # one chunk of the quality workload with fused statistics (and without)
+    c = inputs.throughput_quality()
+    g = W.Generator(c["num_streams"], pool_n=c["pool_n"], R=c["R"])
+    g.seed(c["seed"])
+    o = torch.empty(int(c["counts"].sum()), dtype=torch.float32, device="cuda")
+    buf = g.stats_buffer()
+    ms = steady(lambda: g.fill_stats_into(o, c["streams"], c["counts"], buf, stream), reps=2)
+    ms0 = steady(lambda: g.fill_into(o, c["streams"], c["counts"], stream), reps=2)
+    res["quality_chunk"] = {"config": "262144 streams x 2^16 (one of 4 chunks), pool 4096 "
+                                      "binary32, R=2, fused statistics",
+                            "ms_with_stats": ms, "normals_per_s_with_stats": o.numel() / ms * 1e3,
+                            "ms_without_stats": ms0,
+                            "normals_per_s_without_stats": o.numel() / ms0 * 1e3}
+    g.close()
+    del o
+    torch.cuda.empty_cache()
     return res
 
 
@@ -264,10 +371,20 @@ def main():
                      "kernel": "k_fill (pool 4096 binary32, binary32 output)", "kernel_ms": avg_ms,
                      "bytes_per_launch": alg_bytes, "output_bytes": out_b,
                      "state_bytes": state_b,
-                     "output_write_frac": out_b / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                     "output_write_frac": out_b / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     # every call reads and writes each stream's pool: a third of the
+                     # bytes here, so 70% of 8 TB/s in output writes alone would need
+                     # output_write_frac * 8 TB/s * bytes_per_launch / output_bytes in all
+                     "state_io_frac": state_b / alg_bytes},
     }
     if not args.no_comparators:
         rec["comparators"] = comparators(W, w, out, stream)
+        ceil = rec["comparators"]["traffic_ceiling"]["ms"]
+        rec["roofline"]["frac_of_traffic_ceiling"] = ceil / avg_ms
+    if not args.no_workloads:
+        del out
+        torch.cuda.empty_cache()
+        rec["workloads"] = other_workloads(W, stream)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

@@ -52,51 +52,56 @@ __global__ __launch_bounds__(kBlock) void k_store(uint32_t *__restrict__ dst, ui
   }
 }
 
+// Pure stores in runs: a persistent grid in which workgroup b writes runs
+// b, b + grid, ... of `run` consecutive words (dword stores, one word per lane
+// per instruction), the last run cut at nwords.
+__global__ __launch_bounds__(kBlock) void k_store_runs(uint32_t *__restrict__ dst, uint64_t nwords,
+                                                       uint32_t run) {
+  const uint64_t nruns = (nwords + run - 1) / run;
+  for (uint64_t j = blockIdx.x; j < nruns; j += gridDim.x) {
+    const uint64_t lo = j * run;
+    const uint64_t hi = lo + run < nwords ? lo + run : nwords;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) dst[i] = 0u;
+  }
+}
+
 // ---- the fill's traffic, no arithmetic ------------------------------------------
-// Work item j: its pool (n binary32) and a 64-byte header at
-// state + j * (4n + 64); outputs in pools of n-1 values, each wave storing 64
-// consecutive words per instruction, as the generator does.
+// A plain streaming copy of one fill's bytes: work item j (one workgroup)
+// reads its pool (n binary32) and 64-byte header at state + j (4n + 64),
+// writes per_stream binary32 values to out + j per_stream as consecutive
+// coalesced words (each wave 64 words per instruction), and writes the pool
+// and header back.  The same bytes as the generator's fill of that request,
+// in the simplest order: the practical ceiling of the fill on this traffic.
 template <int NQ>
 __global__ __launch_bounds__(kBlock) void k_traffic(unsigned char *__restrict__ state,
                                                     float *__restrict__ out, uint32_t n,
                                                     uint64_t per_stream) {
   const uint32_t j = blockIdx.x;
-  const uint32_t L = n / 4;
   const uint32_t tid = threadIdx.x;
   float *pool = reinterpret_cast<float *>(state + size_t(j) * (size_t(n) * 4 + 64));
   uint4 *hdr = reinterpret_cast<uint4 *>(state + size_t(j) * (size_t(n) * 4 + 64) + size_t(n) * 4);
-  float y[NQ][4];
+  float y[4 * NQ];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int c = 0; c < NQ; ++c) y[c][m] = pool[m * L + c * kBlock + tid];
+  for (int k = 0; k < 4 * NQ; ++k) y[k] = pool[k * kBlock + tid];
   uint4 h = make_uint4(0, 0, 0, 0);
   if (tid < 4) h = hdr[tid];
-  uint64_t obase = uint64_t(j) * per_stream;
-  uint64_t count = per_stream;
-  while (count > 0) {
-    // 32-bit min: no 64-bit compare-and-select of a uniform value
-    const uint32_t big = uint32_t((0ull - (count >> 32)) >> 32);
-    const uint32_t take = min(uint32_t(count) | big, n - 1);
+  float *o = out + size_t(j) * per_stream;
+  // the values written are the pool's, repeated
+  const uint64_t chunk = uint64_t(4 * NQ) * kBlock;
+  for (uint64_t b = 0; b < per_stream; b += chunk) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int c = 0; c < NQ; ++c) {
-        const uint32_t i = m * L + c * kBlock + tid;
-        if (i < take) out[obase + i] = y[c][m];
-      }
-    obase += take;
-    count -= take;
+    for (int k = 0; k < 4 * NQ; ++k) {
+      const uint64_t i = b + uint64_t(k) * kBlock + tid;
+      if (i < per_stream) o[i] = y[k];
+    }
   }
   // the empty asm keeps the compiler from dropping the write-back of values
   // it has just loaded from the same addresses
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int c = 0; c < NQ; ++c) {
-      asm volatile("" : "+v"(y[c][m]));
-      pool[m * L + c * kBlock + tid] = y[c][m];
-    }
+  for (int k2 = 0; k2 < 4 * NQ; ++k2) {
+    asm volatile("" : "+v"(y[k2]));
+    pool[k2 * kBlock + tid] = y[k2];
+  }
   if (tid < 4) {
     asm volatile("" : "+v"(h.x), "+v"(h.y), "+v"(h.z), "+v"(h.w));
     hdr[tid] = h;
@@ -179,9 +184,21 @@ extern "C" {
 
 wn_status wn_bench_store(void *dst, uint64_t bytes, uint32_t width_dwords, void *hip_stream) {
   const bool nt = (width_dwords & 0x100u) != 0;
+  const bool runs = (width_dwords & 0x200u) != 0;
   width_dwords &= 0xFFu;
   if (!dst || bytes % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0 ||
-      (width_dwords != 1 && width_dwords != 4)) return WN_EINVAL;
+      (width_dwords != 1 && width_dwords != 4) || (runs && (nt || width_dwords != 1)))
+    return WN_EINVAL;
+  if (runs) {
+    (void)hipGetLastError();  // an earlier call's error is not this launch's
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipLaunchKernelGGL(k_store_runs, dim3(uint32_t(cus) * 4), dim3(kBlock), 0,
+                       static_cast<hipStream_t>(hip_stream), static_cast<uint32_t *>(dst),
+                       bytes / 4, 65536u);
+    return launch_status("wn_bench_store");
+  }
   (void)hipGetLastError();  // an earlier call's error is not this launch's
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const uint64_t nvec = bytes / (4 * width_dwords);

@@ -275,11 +275,15 @@ struct Half {
   uint16_t u;
 };
 
+// Binary32 to bfloat16, rounded to nearest even: the hardware conversion
+// (v_cvt_pk_bf16_f32).  On MI355X it equals round-to-nearest-even written out
+// in integer arithmetic on every binary32 bit pattern that is not a NaN
+// (checked exhaustively over all 2^32 patterns, denormals kept); the
+// generator never produces a NaN.  The empty asm keeps the binary32 value as
+// computed.
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return uint16_t((u >> 16) | 0x0040u);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return uint16_t(u >> 16);
+  asm volatile("" : "+v"(f));
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f));
 }
 // The binary32 value must exist before the conversion: without the empty asm
 // the compiler folds "multiply then convert" into v_fma_mixlo_f16, which rounds
@@ -368,7 +372,7 @@ struct StatsAcc {
 // ---- LDS layout ---------------------------------------------------------------------
 // LDS of one workgroup (all dynamic, from local address 0):
 //   pool buffer(s)              n * sizeof(T), twice with two buffers
-//   sum-of-squares scratch      4 waves x min(NQ, 4) x 64 binary64 (NQ > 1 only)
+//   sum-of-squares scratch      4 waves x 2 x 64 binary64 (NQ > 1 only)
 //   partial-sum slots           two sets of 4 * NQ binary64, used alternately
 //   4 words for broadcasts (0: seeding; 1, 2: the pair form's pool counts;
 //     3: spare, the persistent kernel's item word when it is the last)
@@ -379,7 +383,9 @@ constexpr size_t kMiscLds = 4 * sizeof(uint64_t);
 
 __host__ __device__ constexpr uint32_t nq_of(uint32_t n) { return n >= 1024 ? n / 1024 : 1u; }
 // columns per thread handled in one round of the sum-of-squares transposition
-__host__ __device__ constexpr uint32_t sq_round(uint32_t nq) { return nq < 4 ? nq : 4u; }
+// (two: a 4 KiB scratch keeps three workgroups per compute unit for the
+// statistics kernel, with two pool buffers and its histogram)
+__host__ __device__ constexpr uint32_t sq_round(uint32_t nq) { return nq < 2 ? nq : 2u; }
 
 template <typename T>
 __host__ __device__ constexpr size_t pool_lds(uint32_t n, bool db) {

@@ -1,8 +1,9 @@
 """GPU checks of the measurement kernels (include/wn_bench.h).
 
 They are not the generator, but the benchmark quotes them, so they must do
-what they claim: the store kernel writes every byte, the traffic kernel moves
-the fill's bytes without changing the state, and the Box-Muller comparator
+what they claim: the store kernels write every byte and nothing past it, the
+traffic kernel moves the fill's bytes (a plain copy) without changing the
+state, and the Box-Muller comparator
 produces N(0,1) values from the published Philox4x32-10 stream.
 """
 import ctypes as C
@@ -26,13 +27,15 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-@pytest.mark.parametrize("width", [1, 4])
-def test_store_ceiling_writes_everything(width):
+@pytest.mark.parametrize("width", [1, 4, 1 | 0x100, 1 | 0x200])
+@pytest.mark.parametrize("words", [1 << 20, (1 << 20) + 1236])
+def test_store_ceiling_writes_everything(width, words):
     import torch
-    t = torch.full((1 << 20,), 7, dtype=torch.int32, device="cuda")
-    W.wn_bench_store(_ptr(t), t.numel() * 4, width, _stream())
+    t = torch.full((words + 64,), 7, dtype=torch.int32, device="cuda")
+    W.wn_bench_store(_ptr(t), words * 4, width, _stream())
     torch.cuda.synchronize()
-    assert int(t.abs().sum()) == 0
+    assert int(t[:words].abs().sum()) == 0
+    assert bool((t[words:] == 7).all())  # nothing past the end
 
 
 def test_traffic_kernel_pattern():
@@ -47,8 +50,9 @@ def test_traffic_kernel_pattern():
     s = before.cpu().numpy()
     o = out.cpu().numpy().view(np.uint32)
     for j in (0, 17, ns - 1):
+        # a plain copy: output word i of stream j is pool word i mod n
         pool = s[j * (n * 4 + 64): j * (n * 4 + 64) + n * 4].view(np.uint32)
-        want = np.concatenate([pool[: n - 1]] * (per // (n - 1) + 1))[:per]
+        want = np.tile(pool, per // n + 1)[:per]
         np.testing.assert_array_equal(o[j * per: (j + 1) * per], want)
 
 
