@@ -325,7 +325,9 @@ __device__ __forceinline__ double widen(double v) { return v; }
 __device__ __forceinline__ float widen(Bf16 v) { return __uint_as_float(uint32_t(v.u) << 16); }
 __device__ __forceinline__ float widen(Half v) { return float(__builtin_bit_cast(_Float16, v.u)); }
 
-constexpr uint32_t kHistSlots = kHistBins + 2;  // bins, then below -8 and at or above 8
+// LDS histogram slots: 0 counts y < -8, 1 + b bin b (floor(256 y) + 2048 = b),
+// kHistBins + 1 counts y >= 8
+constexpr uint32_t kHistSlots = kHistBins + 2;
 // statistics LDS: 16 partial-sum slots, 4 per-wave flag words, the histogram
 constexpr size_t kStatsLds =
     16 * sizeof(double) + 4 * sizeof(uint32_t) + ((kHistSlots * 4 + 15) / 16) * 16;
@@ -336,7 +338,9 @@ static_assert(((kHistSlots * 4 + 15) / 16) * 16 - kHistSlots * 4 >= 8,
 // workgroup's LDS histogram: bin floor(256 y) + 2048 for y in [-8, 8).  The
 // square y2 is rounded once (exact for a binary32 y); y^3 and y^4 enter their
 // sums through one fused multiply-add each.  The bin is taken in the value's
-// own type, where 256 y is exact.
+// own type, where 256 y is exact, with no branch: floor(256 y) converted to an
+// integer (out-of-range values saturate) and clamped to [-2049, 2048], so that
+// -2049 stands for y < -8 and 2048 for y >= 8; the slot is that plus 2049.
 struct StatsAcc {
   double m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
   uint32_t *hist = nullptr;
@@ -347,17 +351,17 @@ struct StatsAcc {
     m3 = __fma_rn(y2, y, m3);
     m4 = __fma_rn(y2, y2, m4);
   }
+  // floor(z) clamped to [-2049, 2048] (in floating point, so that the
+  // conversion to an integer is always in range)
+  __device__ __forceinline__ static int32_t bin_of(float z) {
+    return int32_t(__builtin_amdgcn_fmed3f(floorf(z), -2049.0f, 2048.0f));
+  }
+  __device__ __forceinline__ static int32_t bin_of(double z) {
+    return int32_t(fmin(fmax(floor(z), -2049.0), 2048.0));
+  }
   template <typename V>
   __device__ __forceinline__ void bin(V y) {
-    const V z = y * V(256);
-    uint32_t slot;
-    if (!(z >= V(-2048)))
-      slot = kHistBins;
-    else if (z >= V(2048))
-      slot = kHistBins + 1;
-    else
-      slot = uint32_t(int32_t(floor(z)) + 2048);
-    atomicAdd(hist + slot, 1u);
+    atomicAdd(hist + (bin_of(y * V(256)) + 2049), 1u);
   }
   __device__ __forceinline__ void add(float y) {
     moments(double(y));
@@ -1020,8 +1024,8 @@ __device__ __forceinline__ void hist_flush(uint32_t *hist, StatsOut *out) {
   for (uint32_t b = threadIdx.x; b < kHistSlots; b += blockDim.x) {
     const uint32_t v = hist[b];
     if (v) {
-      unsigned long long *dst = b < kHistBins ? reinterpret_cast<unsigned long long *>(out->hist + b)
-                                : b == kHistBins ? reinterpret_cast<unsigned long long *>(&out->below)
+      unsigned long long *dst = b == 0 ? reinterpret_cast<unsigned long long *>(&out->below)
+                                : b <= kHistBins ? reinterpret_cast<unsigned long long *>(out->hist + (b - 1))
                                                  : reinterpret_cast<unsigned long long *>(&out->above);
       atomicAdd(dst, (unsigned long long)v);
       hist[b] = 0u;
