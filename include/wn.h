@@ -68,6 +68,21 @@ typedef enum { WN_X_PREVIOUS = 0, WN_X_CURRENT = 1 } wn_chi2_source;
  * log2(n) + 4: a pair-join grows dependency sets half as fast. */
 typedef enum { WN_TRANSFORM_A4 = 0, WN_TRANSFORM_ROTATION = 1 } wn_transform;
 
+/* The law of the values returned.  Section 5 names the exponential (E x = 1,
+ * x >= 0) beside the normal as a maximum-entropy law but gives no transform
+ * for it.  WN_EXPONENTIAL returns, for each pool, position j = m*(n/4) + q
+ * (m = 0, 1; q a column of the pool's 4 rows of n/4) as ((a*a) + (b*b)) * 1/2
+ * in the pool type, where a and b are the scaled normal values of rows m and
+ * m+2 of column q: (a^2 + b^2)/2 is exactly Exp(1) for independent N(0,1) a
+ * and b (chi-square with two degrees of freedom, halved).  The pairs are
+ * disjoint and leave out only the withheld value and its partner, so a pool
+ * gives n/2 - 1 values, and with the chi-square rescale their sum varies from
+ * pool to pool like the maximum-entropy argument asks (Section 5.5).  Counts
+ * and cursors are in values of the chosen law.  With WN_EXPONENTIAL, mean and
+ * stddev must keep their defaults, emit_stride must be 1, and wn_fill_stats
+ * (whose statistics are those of normal values) is not offered. */
+typedef enum { WN_NORMAL = 0, WN_EXPONENTIAL = 1 } wn_variate;
+
 typedef struct {
   uint32_t struct_size;       /* sizeof(wn_config), or WN_CONFIG_V1_SIZE (fields up to device)
                                  or WN_CONFIG_V2_SIZE (fields up to stddev) */
@@ -89,7 +104,7 @@ typedef struct {
                                  of its underlying sequence, starting with the first; the
                                  option of Section 5.7 that keeps only some of the values.  Pool
                                  statistics describe the underlying pools. */
-  uint32_t reserved;          /* 0 */
+  wn_variate variate;         /* WN_NORMAL (0, the default) or WN_EXPONENTIAL */
 } wn_config;
 #define WN_CONFIG_V1_SIZE 40u
 #define WN_CONFIG_V2_SIZE 64u

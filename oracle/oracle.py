@@ -21,7 +21,8 @@ class _Config(C.Structure):
     _fields_ = [(name, C.c_uint32) for name in (
         "num_streams", "default_pool_n", "R", "pool_f64", "chi2", "K", "hazard", "warmup",
         "trace", "x_current", "transform", "emit_stride")] + [("mean", C.c_double),
-                                                              ("stddev", C.c_double)]
+                                                              ("stddev", C.c_double),
+                                                              ("variate", C.c_uint32)]
 
 
 class StreamInfo(C.Structure):
@@ -231,7 +232,7 @@ class Generator:
 
     def __init__(self, num_streams, pool_n=4096, R=2, pool_dtype="f32", chi2=CHI2_CUBIC,
                  K=16, hazard=HAZ_NONE, warmup=0, trace=False, x_current=False, transform=0,
-                 mean=0.0, stddev=1.0, emit_stride=1):
+                 mean=0.0, stddev=1.0, emit_stride=1, variate=0):
         self.num_streams = int(num_streams)
         per_stream = None
         if np.ndim(pool_n) > 0:
@@ -243,7 +244,7 @@ class Generator:
         self.pool_f64 = pool_dtype in ("f64", "float64", np.float64)
         cfg = _Config(self.num_streams, default, R, int(self.pool_f64), chi2, K, hazard, warmup,
                       int(bool(trace)), int(bool(x_current)), transform, emit_stride, mean,
-                      stddev)
+                      stddev, variate)
         self._pool_n = per_stream
         self._h = lib().orc_create(C.byref(cfg),
                                    per_stream.ctypes.data if per_stream is not None else None)

@@ -446,7 +446,23 @@ struct Config {
   double mean;         // added to every output when non-zero
   double stddev;       // folded into the scale
   uint32_t stride;     // the stream returns every stride-th underlying value
+  uint32_t variate;    // 0: normal; 1: exponential (R23)
 };
+
+// R23: exponential variates (Section 5 names the exponential as the
+// maximum-entropy law under E x = 1, x >= 0; the paper gives no transform).
+// If a and b are independent N(0,1), (a^2 + b^2)/2 is exactly Exp(1) (the
+// chi-square law with two degrees of freedom, halved).  A pool of the normal
+// generator is 4 rows of L; its exponential position j = m*L + q (m = 0, 1)
+// pairs the scaled values of rows m and m+2 in column q, which pairs every
+// element once and leaves out only the withheld element n-1 with its partner
+// (row 1, column L-1): n/2 - 1 exponential values per pool.  With the
+// chi-square rescale the sum of a pool's exponential values is half the
+// scaled sum of squares of its n-2 paired normals, so it varies from pool to
+// pool as the maximum-entropy argument requires (Section 5.5).
+inline uint32_t positions_per_pool(uint32_t n, uint32_t variate) {
+  return variate == 1 ? n / 2 - 1 : n - 1;
+}
 
 inline uint32_t ilog2(uint32_t v) {
   uint32_t r = 0;
@@ -487,7 +503,7 @@ struct Gen {
     st.qlast = sum_of_squares(st.P.data(), st.n);
     st.xnext = double(st.P[st.n - 1]);
     st.k = 0;
-    st.cursor = st.n - 1;
+    st.cursor = positions_per_pool(st.n, cfg.variate);
     st.f = 1.0;
     st.trace.clear();
     st.ready = true;
@@ -546,6 +562,31 @@ struct Gen {
     if (!st.ready) init_stream(s);
     const Chi2Consts cc = chi2_consts(st.n);
     const T muT = T(cfg.mean);
+    if (cfg.variate == 1) {
+      // R23: position j = m*L + q of a pool is (a*a + b*b) * 1/2 in the pool
+      // type, a and b the scaled values of rows m and m+2 in column q
+      const uint32_t np = positions_per_pool(st.n, 1);
+      const uint32_t L = st.n / 4;
+      while (count > 0) {
+        if (st.cursor == np) produce_pool(st, cc);
+        const T fT = T(st.f * cfg.stddev);
+        const uint64_t take = std::min<uint64_t>(count, np - st.cursor);
+        for (uint64_t j = 0; j < take; ++j) {
+          const uint32_t pos = st.cursor + uint32_t(j);
+          const uint32_t m = pos / L, q = pos % L;
+          const T a = st.P[m * L + q] * fT;
+          const T b = st.P[(m + 2) * L + q] * fT;
+          const T aa = a * a;
+          const T bb = b * b;
+          const T e = (aa + bb) * T(0.5);
+          store_out(out, off + j, e, dtype);
+        }
+        st.cursor += uint32_t(take);
+        off += take;
+        count -= take;
+      }
+      return;
+    }
     if (cfg.stride > 1) {
       // Section 5.7's option of keeping only some values, for any stride t: the stream is
       // every t-th value of the underlying sequence (the n-1 emitted positions
@@ -612,6 +653,7 @@ struct orc_config {
   uint32_t emit_stride;  // 0 or 1: every value; t: every t-th value
   double mean;
   double stddev;
+  uint32_t variate;      // 0: normal; 1: exponential (R23)
 };
 
 struct orc_stream_info {
@@ -751,10 +793,14 @@ void *orc_create(const orc_config *cfg, const uint32_t *pool_n) {
   if (!cfg || cfg->num_streams == 0 || cfg->R == 0) return nullptr;
   auto *g = new OrcGen();
   g->pool_f64 = cfg->pool_f64;
-  if (!(cfg->stddev > 0.0) || cfg->transform > 1 || cfg->emit_stride > 16) return nullptr;
+  if (!(cfg->stddev > 0.0) || cfg->transform > 1 || cfg->emit_stride > 16 || cfg->variate > 1 ||
+      (cfg->variate == 1 && (cfg->mean != 0.0 || cfg->stddev != 1.0 || cfg->emit_stride > 1))) {
+    delete g;
+    return nullptr;
+  }
   Config c{cfg->num_streams, cfg->R,         cfg->chi2,      cfg->K,    cfg->hazard, cfg->warmup,
            cfg->trace,       cfg->x_current, cfg->transform, cfg->mean, cfg->stddev,
-           cfg->emit_stride ? cfg->emit_stride : 1u};
+           cfg->emit_stride ? cfg->emit_stride : 1u, cfg->variate};
   std::vector<uint32_t> ns(cfg->num_streams);
   for (uint32_t s = 0; s < cfg->num_streams; ++s) {
     ns[s] = pool_n ? pool_n[s] : cfg->default_pool_n;

@@ -124,6 +124,7 @@ struct wn_gen {
   uint32_t num_streams = 0;
   uint32_t R = 1, K = 0, chi2 = 0;
   uint32_t x_current = 0, transform = 0, stride = 1;
+  uint32_t variate = 0;  // 0 normal, 1 exponential
   double mean = 0.0, stddev = 1.0;
   bool pool_f64 = false;
   std::vector<uint32_t> pool_n;     // per stream
@@ -164,6 +165,11 @@ struct wn_gen {
 
 namespace {
 
+// values a pool of n gives: n - 1 normals, or n/2 - 1 exponentials
+uint32_t positions_per_pool(const wn_gen *g, uint32_t n) {
+  return g->variate ? n / 2 - 1 : n - 1;
+}
+
 wn::KernelCommon common(const wn_gen *g, uint32_t n) {
   wn::KernelCommon c;
   c.hdr = g->d_hdr;
@@ -178,6 +184,7 @@ wn::KernelCommon common(const wn_gen *g, uint32_t n) {
   c.transform = g->transform;
   c.unit_sigma = g->stddev == 1.0 ? 1u : 0u;
   c.stride = g->stride;
+  c.expo = g->variate;
   c.sigma = g->stddev;
   c.mu = g->mean;
   for (int i = 0; i < wn::kNumSizes; ++i) {
@@ -231,7 +238,7 @@ hipError_t record_last(wn_gen *g, hipStream_t st) {
 namespace {
 struct StateBlobHeader {  // prefix of a saved state
   uint64_t magic;         // "WNSTATE1"
-  uint32_t num_streams, pool_f64, R, K, chi2, x_current, transform, stride;
+  uint32_t num_streams, pool_f64, R, K, chi2, x_current, transform, stride, variate, pad;
   double mean, stddev;
   uint64_t arena_bytes, hdr_bytes;
 };
@@ -248,6 +255,7 @@ StateBlobHeader blob_header(const wn_gen *g) {
   h.x_current = g->x_current;
   h.transform = g->transform;
   h.stride = g->stride;
+  h.variate = g->variate;
   h.mean = g->mean;
   h.stddev = g->stddev;
   h.arena_bytes = g->arena_bytes;
@@ -296,6 +304,8 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   const bool v3 = cfg->struct_size == sizeof(wn_config);
   const uint32_t stride = v3 && cfg->emit_stride ? cfg->emit_stride : 1u;
   if (stride > 16) return fail(WN_EINVAL, "wn_create: emit_stride %u, at most 16", stride);
+  const uint32_t variate = v3 ? uint32_t(cfg->variate) : 0u;
+  if (variate > 1) return fail(WN_EINVAL, "wn_create: unknown variate %u", variate);
   const uint32_t x_src = v2 ? uint32_t(cfg->chi2_source) : 0u;
   const uint32_t transform = v2 ? uint32_t(cfg->transform) : 0u;
   const double mean = v2 ? cfg->mean : 0.0;
@@ -304,6 +314,9 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   if (transform > 1) return fail(WN_EINVAL, "wn_create: unknown transform %u", transform);
   if (!(std::isfinite(mean)) || !(stddev > 0.0) || !std::isfinite(stddev))
     return fail(WN_EINVAL, "wn_create: mean must be finite and stddev finite and positive");
+  if (variate == 1 && (mean != 0.0 || stddev != 1.0 || stride != 1))
+    return fail(WN_EINVAL, "wn_create: exponential variates take mean 0, stddev 1 and "
+                           "emit_stride 1");
   // one-size launches run one workgroup of up to 256 threads per stream: 2^24
   // streams keep a grid within the 2^32 work-items of one dimension
   if (cfg->num_streams == 0 || cfg->num_streams > (1u << 24))
@@ -349,6 +362,7 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   g->x_current = x_src;
   g->transform = transform;
   g->stride = stride;
+  g->variate = variate;
   g->mean = mean;
   g->stddev = stddev;
   g->pool_f64 = cfg->pool_dtype == WN_F64;
@@ -406,7 +420,7 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
     std::memset(&hdr[s], 0, sizeof(wn::StreamHdr));
     hdr[s].pool_off = g->pool_off[s];
     hdr[s].n = g->pool_n[s];
-    hdr[s].cursor = g->pool_n[s] - 1;
+    hdr[s].cursor = positions_per_pool(g, g->pool_n[s]);  // no pool ready
   }
   if ((e = hipMemcpy(g->d_hdr, hdr.data(), hdr.size() * sizeof(wn::StreamHdr),
                      hipMemcpyHostToDevice)) != hipSuccess ||
@@ -675,7 +689,8 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
     // threads, in the plain loop (no statistics, thinning or rotations; pools
     // of at most 4096 values).  With the deferred form on, the items that run
     // alone take it.
-    const uint32_t group = (!stats && g->stride == 1 && g->transform == 0 && max_n <= 4096)
+    const uint32_t group = (!stats && g->stride == 1 && g->transform == 0 && !g->variate &&
+                            max_n <= 4096)
                                ? g->group_items
                                : 0u;
     const size_t entry_slots = group ? (size_t(nbig) * sizeof(uint32_t) + sizeof(wn::WorkItem) - 1) /
@@ -696,7 +711,7 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
       // a pool's time alone grows with n from a fixed part about as large as a
       // 4096-value pool's n-proportional part (2.8, 3.4 and 4.1 thousand cycles
       // for n = 1024, 2048, 4096), so small pools cost more per value
-      const uint64_t pools = counts[j] * g->stride / (n - 1) + 1;
+      const uint64_t pools = counts[j] * g->stride / positions_per_pool(g, n) + 1;
       order.emplace_back(pools * (n + 4096), j);
     }
     std::stable_sort(order.begin(), order.end(),
@@ -880,6 +895,8 @@ wn_status wn_fill_stats(wn_gen *g, uint32_t nreq, const uint32_t *streams, const
   wn_status v = validate_fill(g, "wn_fill_stats", nreq, streams, counts, out, out_dtype, &total);
   if (v != WN_OK) return v;
   if ((v = validate_stats("wn_fill_stats", nreq, counts, stats)) != WN_OK) return v;
+  if (g->variate)
+    return fail(WN_ENOTSUP, "wn_fill_stats: the statistics are those of normal values");
   hipError_t e = hipSetDevice(g->device);
   if (e != hipSuccess) return hip_fail(e, "wn_fill_stats: hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -912,6 +929,7 @@ wn_status wn_fill_stats_noalloc(wn_gen *g, uint32_t nreq, const uint32_t *stream
   wn_status v = validate_fill(g, who, nreq, streams, counts, out, out_dtype, &total);
   if (v != WN_OK) return v;
   if ((v = validate_stats(who, nreq, counts, stats)) != WN_OK) return v;
+  if (g->variate) return fail(WN_ENOTSUP, "%s: the statistics are those of normal values", who);
   if (nreq > wn::kNoAllocRequests)
     return fail(WN_EINVAL, "%s: %u requests, at most %u (the statically allocated partials)", who,
                 nreq, wn::kNoAllocRequests);
@@ -1206,7 +1224,8 @@ wn_status wn_load_state(wn_gen *g, const void *host_buf, size_t bytes) {
   for (uint32_t s = 0; s < g->num_streams; ++s) {
     wn::StreamHdr hs;
     std::memcpy(&hs, src + sizeof(h) + size_t(s) * sizeof(hs), sizeof(hs));
-    if (hs.n != g->pool_n[s] || hs.pool_off != g->pool_off[s] || hs.cursor > hs.n - 1 ||
+    if (hs.n != g->pool_n[s] || hs.pool_off != g->pool_off[s] ||
+        hs.cursor > positions_per_pool(g, hs.n) ||
         (hs.sflags & ~uint16_t(wn::kHeldExtreme | wn::kSeenByStats)) != 0)
       return fail(WN_EINVAL, "wn_load_state: stream %u's saved header does not fit this "
                              "generator (pool size, offset, cursor or flags)", s);

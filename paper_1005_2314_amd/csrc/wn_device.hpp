@@ -923,6 +923,28 @@ struct Engine {
       }
   }
 
+  // Exponential positions [lo, hi) of the pool held in y to out[obase + (j - lo)]:
+  // position j = m*L + c*BD + tid (m = 0, 1) is ((a*a) + (b*b)) * 1/2 in the
+  // pool type, a = T(y[c][m] * fT) and b = T(y[c][m+2] * fT): half the sum of
+  // squares of two scaled values of the pool, rows m and m+2 of one column.
+  template <bool NT, typename O>
+  __device__ __forceinline__ void emit_expo(O *__restrict__ out, uint64_t obase, uint32_t lo,
+                                            uint32_t hi, T fT) const {
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) {
+        const uint32_t j = pos(m, c);
+        if (j >= lo && j < hi) {
+          const T a = y[c][m] * fT;
+          const T b = y[c][m + 2] * fT;
+          const T aa = a * a;
+          const T bb = b * b;
+          put<NT>(out + (obase + (j - lo)), Cast<O>::from(T((aa + bb) * T(0.5))));
+        }
+      }
+  }
+
   // Thinned emission: positions j0, j0 + t, ..., j0 + (take-1) t go to
   // out[obase], out[obase + 1], ... (every t-th value of the stream).
   template <bool NT, bool STATS, typename O>
@@ -1085,7 +1107,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
     h->xnext = last;
     h->qlast = Q;
     h->n = n;
-    h->cursor = uint16_t(n - 1);
+    h->cursor = uint16_t(a.c.expo ? n / 2 - 1 : n - 1);  // no pool ready
     h->sflags = 0;
   }
 }
@@ -1139,6 +1161,9 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     tprev = h->tprev;
   }
   const Chi2Consts &cc = a.c.cc[__builtin_ctz(n) - 4];
+  // values a pool gives: n - 1 normals, or n/2 - 1 exponentials
+  const bool expo = __builtin_amdgcn_readfirstlane(a.c.expo) != 0;
+  const uint32_t np = expo ? n / 2 - 1 : n - 1;
   uint64_t xs = h->xs;
   uint64_t k = h->k;
   const uint64_t k0 = k;
@@ -1155,9 +1180,9 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   // barriers.  Each half publishes its count across the barrier below.
   uint64_t steps = 0;
   if constexpr (PAIR) {  // (the pair form runs without thinning)
-    const uint64_t head = cursor < n - 1 ? take_of(count, n - 1 - cursor) : 0u;
+    const uint64_t head = cursor < np ? take_of(count, np - cursor) : 0u;
     const uint64_t rest = count - head;
-    const uint64_t mine = rest == 0 ? 0 : (rest - 1) / (n - 1) + 1;
+    const uint64_t mine = rest == 0 ? 0 : (rest - 1) / np + 1;
     if (e.tid == 0) *misc_word(smem, misc_off<T>(nmax, DB), 1 + int(half)) = mine;
   }
   e.sync();
@@ -1199,11 +1224,15 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
     cur = j0 + (take - 1) * t + 1;
     return take;
   };
-  if (cursor < n - 1) {
+  if (cursor < np) {
     const T fT = scale_of(f);
     uint32_t take;
     if (t > 1) {
       take = emit_thinned(cursor, fT);
+    } else if (expo) {
+      take = take_of(count, np - cursor);
+      e.template emit_expo<NT>(out, obase, cursor, cursor + take, fT);
+      cursor += take;
     } else {
       take = take_of(count, n - 1 - cursor);
       if (has_mu)
@@ -1223,7 +1252,7 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   const bool rescale = a.c.chi2 != kChi2Off;
   bool deferred = false;
   if constexpr (DEFER) {
-    if (t == 1) {
+    if (t == 1 && !expo) {
       deferred = true;
       // kernel-argument values the chain needs, read before the loop
       const Chi2Consts ccv = cc;
@@ -1350,6 +1379,10 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
       ph_next = (ph_next + (n - 1) % t) % t;
       cursor = 0;
       take = emit_thinned(cursor, fT);
+    } else if (expo) {
+      take = take_of(count, np);
+      e.template emit_expo<NT>(out, obase, 0, take, fT);
+      cursor = take;
     } else {
       take = take_of(count, n - 1);
       if (has_mu)

@@ -86,7 +86,7 @@ struct KernelCommon {
   uint32_t transform;  // 0: the 4x4 family A1 D_k; 1: plane rotations
   uint32_t unit_sigma; // 1 when sigma == 1 (the scale is T(f) itself)
   uint32_t stride;     // thinning: every stride-th value of the underlying sequence (1 = all)
-  uint32_t pad2_;
+  uint32_t expo;       // 1: exponential variates, (a^2 + b^2)/2 of paired rows, n/2 - 1 per pool
   double sigma;        // folded into the scale: T(f * sigma)
   double mu;
   Chi2Consts cc[kNumSizes];  // per pool size, index log2(n) - 4

@@ -110,7 +110,8 @@ hipError_t fill_v(const FillArgs &a, hipStream_t st) {
 // the overlap saves), and persistent launches whose pools are at most 4096
 // (items of 4096 there keep the plain loop).
 inline bool defer_applies(const FillArgs &a, uint32_t max_n, uint32_t limit) {
-  return a.defer && !a.partials && a.c.stride == 1 && max_n >= 1024 && max_n <= limit;
+  return a.defer && !a.partials && a.c.stride == 1 && !a.c.expo && max_n >= 1024 &&
+         max_n <= limit;
 }
 
 template <typename T, typename O, int NQ, bool ROT>

@@ -29,6 +29,7 @@ EXPORTED = ("wn_create", "wn_seed", "wn_fill", "wn_sync", "wn_get_stream", "wn_d
 
 
 WN_X_PREVIOUS, WN_X_CURRENT = 0, 1
+WN_NORMAL, WN_EXPONENTIAL = 0, 1
 WN_TRANSFORM_A4, WN_TRANSFORM_ROTATION = 0, 1
 WN_CONFIG_V1_SIZE = 40
 WN_CONFIG_V2_SIZE = 64
@@ -40,7 +41,7 @@ class wn_config(C.Structure):
                 ("passes_per_output", C.c_uint32), ("pool_dtype", C.c_int),
                 ("chi2", C.c_int), ("renorm_period", C.c_uint32), ("device", C.c_int),
                 ("chi2_source", C.c_int), ("transform", C.c_int), ("mean", C.c_double),
-                ("stddev", C.c_double), ("emit_stride", C.c_uint32), ("reserved", C.c_uint32)]
+                ("stddev", C.c_double), ("emit_stride", C.c_uint32), ("variate", C.c_int)]
 
 
 class wn_stream_info(C.Structure):
@@ -228,7 +229,7 @@ def wn_bench_box_muller(out_ptr, count, out_dtype, seed, fast=False, stream=None
 
 def make_config(num_streams, pool_n=4096, R=2, pool_dtype=WN_F32, chi2=WN_CHI2_CUBIC, K=16,
                 device=0, chi2_source=WN_X_PREVIOUS, transform=WN_TRANSFORM_A4, mean=0.0,
-                stddev=1.0, emit_stride=1):
+                stddev=1.0, emit_stride=1, variate=WN_NORMAL):
     cfg = wn_config()
     cfg.struct_size = C.sizeof(wn_config)
     cfg.num_streams = int(num_streams)
@@ -250,6 +251,7 @@ def make_config(num_streams, pool_n=4096, R=2, pool_dtype=WN_F32, chi2=WN_CHI2_C
     cfg.mean = float(mean)
     cfg.stddev = float(stddev)
     cfg.emit_stride = int(emit_stride)
+    cfg.variate = int(variate)
     return cfg, keep
 
 
@@ -320,9 +322,9 @@ class Generator:
 
     def __init__(self, num_streams, pool_n=4096, R=2, pool_dtype=WN_F32, chi2=WN_CHI2_CUBIC,
                  K=16, device=0, chi2_source=WN_X_PREVIOUS, transform=WN_TRANSFORM_A4,
-                 mean=0.0, stddev=1.0, emit_stride=1):
+                 mean=0.0, stddev=1.0, emit_stride=1, variate=WN_NORMAL):
         self.cfg, keep = make_config(num_streams, pool_n, R, pool_dtype, chi2, K, device,
-                                     chi2_source, transform, mean, stddev, emit_stride)
+                                     chi2_source, transform, mean, stddev, emit_stride, variate)
         self.num_streams = int(num_streams)
         self.pool_f64 = pool_dtype == WN_F64
         self.device = device

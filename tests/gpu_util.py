@@ -24,11 +24,13 @@ def to_numpy_bits(t):
 class Pair:
     """A GPU generator and an oracle generator with the same configuration."""
 
-    def __init__(self, num_streams, pool_n=1024, R=2, pool="f32", chi2=0, K=16, seed=1):
+    def __init__(self, num_streams, pool_n=1024, R=2, pool="f32", chi2=0, K=16, seed=1,
+                 variate=0):
         pool_dtype = W.WN_F64 if pool == "f64" else W.WN_F32
         self.gpu = W.Generator(num_streams, pool_n=pool_n, R=R, pool_dtype=pool_dtype,
-                               chi2=chi2, K=K)
-        self.orc = O.Generator(num_streams, pool_n=pool_n, R=R, pool_dtype=pool, chi2=chi2, K=K)
+                               chi2=chi2, K=K, variate=variate)
+        self.orc = O.Generator(num_streams, pool_n=pool_n, R=R, pool_dtype=pool, chi2=chi2, K=K,
+                               variate=variate)
         self.gpu.seed(seed)
         self.orc.seed(seed)
 

@@ -36,6 +36,7 @@ def test_config_struct_layout():
     # version 2 adds two enums and two doubles, version 3 the output stride
     assert W.wn_config.chi2_source.offset == W.WN_CONFIG_V1_SIZE == 40
     assert W.wn_config.emit_stride.offset == W.WN_CONFIG_V2_SIZE == 64
+    assert W.wn_config.variate.offset == 68
     assert C.sizeof(W.wn_config) == 72
     assert C.sizeof(W.wn_stream_info) == 48
     assert C.sizeof(W.wn_stats) == 8 * (1 + 4 + 2 + 1 + 2 + 1 + 1) + 8 * W.HIST_BINS + 16
@@ -65,7 +66,8 @@ def test_older_config_versions_accepted_and_new_fields_validated():
 @pytest.mark.parametrize("kw", [
     dict(num_streams=0), dict(num_streams=(1 << 24) + 1), dict(pool_n=1000), dict(pool_n=8), dict(pool_n=32768),
     dict(R=0), dict(R=65), dict(pool_dtype=W.WN_BF16), dict(chi2=7),
-    dict(pool_n=[1024, 3000])])
+    dict(pool_n=[1024, 3000]), dict(variate=2), dict(variate=W.WN_EXPONENTIAL, mean=1.0),
+    dict(variate=W.WN_EXPONENTIAL, stddev=0.5), dict(variate=W.WN_EXPONENTIAL, emit_stride=4)])
 def test_bad_config_is_einval(kw):
     args = dict(num_streams=2, pool_n=1024, R=2, pool_dtype=W.WN_F32, chi2=W.WN_CHI2_CUBIC)
     args.update(kw)

@@ -125,7 +125,7 @@ def test_request_validation_messages_and_total_cap():
 
 
 def test_load_state_rejects_headers_that_do_not_fit():
-    """A state blob is a 72-byte configuration header, then one 64-byte header
+    """A state blob is a 80-byte configuration header, then one 64-byte header
     per stream (pool size at byte 48, cursor at 52, flags at 54), then the
     pools.  Headers that disagree with the generator's own pools are refused
     and nothing is loaded."""
@@ -139,7 +139,7 @@ def test_load_state_rejects_headers_that_do_not_fit():
     for stream, offset, fmt, value in ((1, 48, "<I", 2048), (0, 52, "<H", 1024),
                                        (2, 52, "<H", 60000), (1, 54, "<H", 8), (0, 40, "<Q", 1 << 40)):
         bad = bytearray(blob)
-        struct.pack_into(fmt, bad, 72 + 64 * stream + offset, value)
+        struct.pack_into(fmt, bad, 80 + 64 * stream + offset, value)
         with pytest.raises(W.WnError) as ei:
             g.load_state(bytes(bad))
         assert ei.value.status == W.WN_EINVAL, (stream, offset)
