@@ -294,6 +294,29 @@ __device__ __forceinline__ uint16_t f16_bits(float f) {
   return __builtin_bit_cast(uint16_t, h);
 }
 
+// Two binary32 values to two 16-bit codes in one conversion (the first in
+// the low half): the same round-to-nearest-even as one at a time, with each
+// binary32 value pinned first as above.
+typedef float F32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 Bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 F16x2 __attribute__((ext_vector_type(2)));
+template <typename O>
+struct Cast2;
+template <>
+struct Cast2<Bf16> {
+  __device__ static uint32_t from(float a, float b) {
+    asm volatile("" : "+v"(a), "+v"(b));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(F32x2{a, b}, Bf16x2));
+  }
+};
+template <>
+struct Cast2<Half> {
+  __device__ static uint32_t from(float a, float b) {
+    asm volatile("" : "+v"(a), "+v"(b));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(F32x2{a, b}, F16x2));
+  }
+};
+
 template <typename O>
 struct Cast;
 template <>
@@ -513,25 +536,26 @@ struct Engine {
   // Gather quadruples from buffer RB and transform them with matrix K.  The
   // row position is (alpha q + gamma) mod L for q = c*BD + tid: one add to
   // step c and one mask per element; row and buffer offsets are immediates.
-  template <int K, int RB>
-  __device__ __forceinline__ void gather_transform(const PassParams &p, bool renorm, double g) {
+  // RN: apply the renormalisation scale g to every gathered value first.
+  template <int K, int RB, bool RN>
+  __device__ __forceinline__ void gather_transform(const PassParams &p, double g) {
     LdsT *P = lds_buf(RB);
     const uint32_t L = len();
     constexpr uint32_t W = sizeof(T);
     const uint32_t mask = (L - 1) * W;  // byte offsets within a row
+    using LdsB = __attribute__((address_space(3))) const unsigned char;
     T x[NQ][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const uint32_t a = p.alpha[m];
       const uint32_t first = __umul24(a * W, tid) + p.gamma[m] * W;
       const uint32_t step = a * bd() * W;
-      using LdsB = __attribute__((address_space(3))) const unsigned char;
       LdsB *row = reinterpret_cast<LdsB *>(P + uint32_t(m) * L);
 #pragma unroll
       for (int c = 0; c < NQ; ++c)
         x[c][m] = *reinterpret_cast<LdsT *>(row + ((first + step * uint32_t(c)) & mask));
     }
-    if (renorm) {
+    if constexpr (RN) {
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -546,8 +570,8 @@ struct Engine {
   // and row 1 at (alpha_1 q + gamma_1) mod H, H = 2L, and writes row 0 and row 1
   // position q, which are elements h*L + c*BD + tid and (h+2)*L + c*BD + tid:
   // the registers y[c][h] and y[c][h+2] of this thread.
-  template <int RB>
-  __device__ __forceinline__ void gather_rotate(const PassParams &p, bool renorm, double g) {
+  template <int RB, bool RN>
+  __device__ __forceinline__ void gather_rotate(const PassParams &p, double g) {
     LdsT *P = lds_buf(RB);
     const uint32_t L = len();
     const uint32_t H = 2 * L;
@@ -568,7 +592,7 @@ struct Engine {
           x[c][h + 2 * r] = *reinterpret_cast<LdsT *>(row + ((first + step * uint32_t(c)) & mask));
       }
     }
-    if (renorm) {
+    if constexpr (RN) {
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -583,17 +607,17 @@ struct Engine {
 
   // ROT (compile-time, so that each family's kernels carry only their own
   // gather): a rotation pass; otherwise A_{k+1} by the runtime k.
-  template <int RB, bool ROT>
-  __device__ __forceinline__ void pass_from(const PassParams &p, bool renorm, double g) {
+  template <int RB, bool ROT, bool RN>
+  __device__ __forceinline__ void pass_from(const PassParams &p, double g) {
     constexpr int WB = DB ? 1 - RB : RB;
     if constexpr (ROT) {
-      gather_rotate<RB>(p, renorm, g);
+      gather_rotate<RB, RN>(p, g);
     } else {
       switch (p.k) {
-        case 0: gather_transform<0, RB>(p, renorm, g); break;
-        case 1: gather_transform<1, RB>(p, renorm, g); break;
-        case 2: gather_transform<2, RB>(p, renorm, g); break;
-        default: gather_transform<3, RB>(p, renorm, g); break;
+        case 0: gather_transform<0, RB, RN>(p, g); break;
+        case 1: gather_transform<1, RB, RN>(p, g); break;
+        case 2: gather_transform<2, RB, RN>(p, g); break;
+        default: gather_transform<3, RB, RN>(p, g); break;
       }
     }
     if (!DB) sync();
@@ -604,19 +628,28 @@ struct Engine {
       for (int c = 0; c < NQ; ++c) W[pos(m, c)] = y[c][m];
   }
 
+  template <bool ROT, bool RN>
+  __device__ __forceinline__ void pass_rn(const PassParams &p, double g) {
+    if (DB && cb != 0) {
+      pass_from<1, ROT, RN>(p, g);
+    } else {
+      pass_from<0, ROT, RN>(p, g);
+    }
+    if (DB) cb ^= 1u;
+  }
+
   // One pass: gather from the LDS pool, transform, write the new pool.  The
   // caller places a barrier before the next read of the pool.  `renorm`
   // applies the renormalisation scale g to every gathered value first (each
   // element is gathered exactly once per pass, so this equals rescaling the
-  // whole pool before the pass).
+  // whole pool before the pass).  The two cases are separate code, so that
+  // the common one carries no select between scaled and plain values.
   template <bool ROT>
   __device__ __forceinline__ void pass(const PassParams &p, bool renorm, double g) {
-    if (DB && cb != 0) {
-      pass_from<1, ROT>(p, renorm, g);
-    } else {
-      pass_from<0, ROT>(p, renorm, g);
-    }
-    if (DB) cb ^= 1u;
+    if (renorm)
+      pass_rn<ROT, true>(p, g);
+    else
+      pass_rn<ROT, false>(p, g);
   }
 
   // The gathers of gather_transform (quadruples) and gather_rotate (pairs,
@@ -898,6 +931,24 @@ struct Engine {
     if (lo == 0 && hi == 4 * L - 1) {
       // a whole pool: every position but the withheld last one
       O *dst = out + obase + tid;
+      if constexpr (sizeof(O) == 2 && NQ % 2 == 0) {
+        // 16-bit outputs: columns c and c+1 converted together
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int c = 0; c < NQ; c += 2) {
+            const uint32_t pk = Cast2<O>::from(float(scaled<MU>(y[c][m], fT, muT)),
+                                               float(scaled<MU>(y[c + 1][m], fT, muT)));
+            const O v0{uint16_t(pk)}, v1{uint16_t(pk >> 16)};
+            put<NT>(dst + (uint32_t(m) * L + uint32_t(c) * bd()), v0);
+            if constexpr (STATS) sa->add(widen(v0));
+            if (m < 3 || c + 1 < NQ - 1 || tid < bd() - 1) {
+              put<NT>(dst + (uint32_t(m) * L + uint32_t(c + 1) * bd()), v1);
+              if constexpr (STATS) sa->add(widen(v1));
+            }
+          }
+        return;
+      }
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -1008,9 +1059,23 @@ __device__ __forceinline__ Engine<T, NQ, false, DB, 128> make_half_engine(unsign
 // select, the compiler has been seen to evaluate the compare into VCC but take
 // the select from a stale SCC (which made the persistent kernel emit whole
 // requests from one pool).
+// A value every lane of the wave holds, as a scalar (so that the item's
+// counters and output offsets live in scalar registers and the stores can
+// address the output with a scalar base and per-lane 32-bit offsets).  The
+// builtin returns int: each word goes back to uint32_t before any widening,
+// so that a low word with bit 31 set is not sign-extended into the high word.
+__device__ __forceinline__ uint32_t uniform32(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_readfirstlane(int(v)));
+}
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t hi = uniform32(uint32_t(v >> 32));
+  const uint32_t lo = uniform32(uint32_t(v));
+  return (uint64_t(hi) << 32) | uint64_t(lo);
+}
+
 __device__ __forceinline__ uint32_t take_of(uint64_t count, uint32_t room) {
   const uint32_t big = uint32_t((0ull - (count >> 32)) >> 32);  // all ones if count >= 2^32
-  return min(uint32_t(count) | big, room);
+  return uniform32(min(uint32_t(count) | big, room));
 }
 
 __device__ __forceinline__ void flag_fault(uint32_t *err, double Q) {
@@ -1138,7 +1203,9 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   static_assert(!(DEFER && STATS), "the deferred form carries no statistics");
   static_assert(!(PAIR && (STATS || DEFER || SMALL)), "the pair form is the plain loop");
   StreamHdr *h = a.c.hdr + s;
-  const uint32_t n = h->n;
+  const uint32_t n = uniform32(h->n);
+  count = uniform64(count);
+  obase = uniform64(obase);
   const uint32_t half = threadIdx.x >> 7;
   auto e = [&]() {
     if constexpr (PAIR)
@@ -1165,12 +1232,12 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   const bool expo = __builtin_amdgcn_readfirstlane(a.c.expo) != 0;
   const uint32_t np = expo ? n / 2 - 1 : n - 1;
   uint64_t xs = h->xs;
-  uint64_t k = h->k;
+  uint64_t k = uniform64(h->k);
   const uint64_t k0 = k;
   double f = h->f;
   double xnext = h->xnext;
   double qlast = h->qlast;
-  uint32_t cursor = h->cursor;
+  uint32_t cursor = uniform32(h->cursor);
   T *gpool = reinterpret_cast<T *>(a.c.arena + h->pool_off);
   O *out = reinterpret_cast<O *>(a.out);
 

@@ -11,6 +11,12 @@ exec-mask operation while a VALU compare into VCC sits in between.
 
 2. The generator kernels must have no static LDS: the pool engine addresses
 its LDS buffers as constants from local address 0.
+
+3. No scalar sign extension of a 32-bit value to 64 bits in the generator
+kernels.  Their counts and output offsets are unsigned; a wave-uniform 64-bit
+offset rebuilt from two 32-bit words must zero-extend the low word (a
+sign-extended low word with bit 31 set fills the high word with ones, and the
+store goes far outside the output).
 """
 import os
 import re
@@ -80,9 +86,27 @@ def static_lds_of_engine_kernels(asm: str):
     return found
 
 
+_SEXT32 = re.compile(r"^\s+s_bfe_i64\s+s\[\d+:\d+\],\s*s\[\d+:\d+\],\s*0x200000\b")
+
+
+def scalar_sign_extensions(asm: str):
+    """(kernel, line) of every scalar 32-to-64-bit sign extension in a
+    generator kernel."""
+    found = []
+    kernel = None
+    for i, line in enumerate(asm.split("\n")):
+        m = re.match(r"^(_Z\S*):", line)
+        if m:
+            kernel = m.group(1)
+        if kernel and any(k in kernel for k in ("k_fill", "k_seed")) and _SEXT32.match(line):
+            found.append((kernel, i + 1))
+    return found
+
+
 def check_library_sources():
     bad = []
     for name, asm in device_asm_texts().items():
         bad += [(name, k, ln) for k, ln in stale_scc_selects(asm)]
         bad += [(name, k, f"static LDS {b}") for k, b in static_lds_of_engine_kernels(asm)]
+        bad += [(name, k, f"sign extension at {ln}") for k, ln in scalar_sign_extensions(asm)]
     return bad

@@ -1,5 +1,7 @@
-"""The device code must not contain selects that can read a stale SCC (see
-paper_1005_2314_amd/isa_check.py); the check cross-compiles on the CPU."""
+"""The device code must not contain selects that can read a stale SCC, static
+LDS in the generator kernels, or scalar sign extensions of 32-bit words into
+64-bit offsets (see paper_1005_2314_amd/isa_check.py); the check
+cross-compiles on the CPU."""
 from paper_1005_2314_amd import isa_check
 
 
@@ -29,3 +31,14 @@ def test_static_lds_checker():
 		.amdhsa_group_segment_fixed_size 64
 """
     assert isa_check.static_lds_of_engine_kernels(asm) == [("_Z6k_fillv", 16)]
+
+
+def test_sign_extension_checker():
+    asm = """_Z6k_fillv:
+	s_mov_b32 s61, s11
+	s_bfe_i64 s[8:9], s[10:11], 0x200000
+	s_or_b64 s[90:91], s[8:9], s[60:61]
+_Z5otherv:
+	s_bfe_i64 s[8:9], s[10:11], 0x200000
+"""
+    assert isa_check.scalar_sign_extensions(asm) == [("_Z6k_fillv", 3)]
