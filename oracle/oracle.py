@@ -254,7 +254,10 @@ class Generator:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_destroy(h)
+            try:
+                lib().orc_destroy(h)
+            except (TypeError, AttributeError):  # interpreter shutdown: module state is gone
+                pass
             self._h = None
 
     def seed(self, seed: int):

@@ -304,10 +304,10 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   const bool v3 = cfg->struct_size == sizeof(wn_config);
   const uint32_t stride = v3 && cfg->emit_stride ? cfg->emit_stride : 1u;
   if (stride > 16) return fail(WN_EINVAL, "wn_create: emit_stride %u, at most 16", stride);
-  const uint32_t variate = v3 ? uint32_t(cfg->variate) : 0u;
+  const uint32_t variate = v3 ? wn::enum_bits(cfg->variate) : 0u;
   if (variate > 1) return fail(WN_EINVAL, "wn_create: unknown variate %u", variate);
-  const uint32_t x_src = v2 ? uint32_t(cfg->chi2_source) : 0u;
-  const uint32_t transform = v2 ? uint32_t(cfg->transform) : 0u;
+  const uint32_t x_src = v2 ? wn::enum_bits(cfg->chi2_source) : 0u;
+  const uint32_t transform = v2 ? wn::enum_bits(cfg->transform) : 0u;
   const double mean = v2 ? cfg->mean : 0.0;
   const double stddev = v2 ? cfg->stddev : 1.0;
   if (x_src > 1) return fail(WN_EINVAL, "wn_create: unknown chi2_source %u", x_src);
@@ -323,10 +323,11 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
     return fail(WN_EINVAL, "wn_create: num_streams must be in [1, 2^24]");
   if (cfg->passes_per_output == 0 || cfg->passes_per_output > 64)
     return fail(WN_EINVAL, "wn_create: passes_per_output must be in [1, 64]");
-  if (cfg->pool_dtype != WN_F32 && cfg->pool_dtype != WN_F64)
+  const uint32_t pool_dtype = wn::enum_bits(cfg->pool_dtype);
+  const uint32_t chi2 = wn::enum_bits(cfg->chi2);
+  if (pool_dtype != WN_F32 && pool_dtype != WN_F64)
     return fail(WN_EINVAL, "wn_create: pool_dtype must be WN_F32 or WN_F64");
-  if (cfg->chi2 < WN_CHI2_CUBIC || cfg->chi2 > WN_CHI2_WH)
-    return fail(WN_EINVAL, "wn_create: unknown chi2 mode %d", int(cfg->chi2));
+  if (chi2 > WN_CHI2_WH) return fail(WN_EINVAL, "wn_create: unknown chi2 mode %u", chi2);
   auto bad_n = [](uint32_t n) { return n < 16 || n > 16384 || !is_pow2(n); };
   if (!cfg->pool_n && bad_n(cfg->default_pool_n))
     return fail(WN_EINVAL, "wn_create: pool size %u is not a power of two in [16, 16384]",
@@ -358,14 +359,14 @@ wn_status wn_create(const wn_config *cfg, wn_gen **out_gen) {
   g->num_streams = cfg->num_streams;
   g->R = cfg->passes_per_output;
   g->K = cfg->renorm_period;
-  g->chi2 = uint32_t(cfg->chi2);
+  g->chi2 = chi2;
   g->x_current = x_src;
   g->transform = transform;
   g->stride = stride;
   g->variate = variate;
   g->mean = mean;
   g->stddev = stddev;
-  g->pool_f64 = cfg->pool_dtype == WN_F64;
+  g->pool_f64 = pool_dtype == WN_F64;
   const size_t esz = g->pool_f64 ? 8 : 4;
   try {
     g->pool_n.resize(cfg->num_streams);
@@ -489,9 +490,9 @@ wn_status validate_fill(wn_gen *g, const char *who, uint32_t nreq, const uint32_
   if (!g) return fail(WN_EINVAL, "%s: generator is NULL", who);
   if (nreq > 0 && (!streams || !counts))
     return fail(WN_EINVAL, "%s: streams/counts are NULL with nreq = %u", who, nreq);
-  if (out_dtype < WN_F64 || out_dtype > WN_F16)
-    return fail(WN_EINVAL, "%s: unknown output dtype %d", who, int(out_dtype));
-  if (!g->pool_f64 && out_dtype == WN_F64)
+  const uint32_t od = wn::enum_bits(out_dtype);
+  if (od > WN_F16) return fail(WN_EINVAL, "%s: unknown output dtype %u", who, od);
+  if (!g->pool_f64 && od == WN_F64)
     return fail(WN_ENOTSUP, "%s: binary64 output needs a binary64 pool", who);
   uint64_t sum = 0;
   enum { kOk, kBadId, kTwice, kTooMany } why = kOk;

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "wn_bench.h"
+#include "wn_internal.hpp"
 
 namespace {
 
@@ -236,8 +237,9 @@ wn_status wn_bench_traffic(void *state, void *out, uint32_t num_streams, uint32_
 wn_status wn_bench_box_muller(void *out, uint64_t count, wn_dtype out_dtype, uint64_t seed,
                               int fast, void *hip_stream) {
   if (!out || count % 4 != 0 || reinterpret_cast<uintptr_t>(out) % 16 != 0) return WN_EINVAL;
-  if (out_dtype != WN_F32 && out_dtype != WN_F64) return WN_EINVAL;
-  if (out_dtype == WN_F64 && fast) return WN_EINVAL;
+  const uint32_t od = wn::enum_bits(out_dtype);
+  if (od != WN_F32 && od != WN_F64) return WN_EINVAL;
+  if (od == WN_F64 && fast) return WN_EINVAL;
   (void)hipGetLastError();  // an earlier call's error is not this launch's
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const uint64_t nquads = count / 4;

@@ -34,6 +34,15 @@
 #include "wn_internal.hpp"
 
 // Internal linkage: each launch unit gets its own copy of these definitions.
+// Debug builds (WN_POISON_LDS=1, the library libwn_poison.so): every LDS pool
+// write is preceded by a fill of the whole buffer with NaN, through a thread
+// mapping other than the writes', and a barrier.  A position that a write
+// misses, or a read that a missing barrier lets run before the writes, then
+// carries NaN into the results, which the parity tests see.
+#ifndef WN_POISON_LDS
+#define WN_POISON_LDS 0
+#endif
+
 namespace wn {
 namespace {
 
@@ -489,8 +498,21 @@ struct Engine {
   }
   __device__ __forceinline__ T *cur() const { return DB ? buf(cb) : base; }
 
+  // WN_POISON_LDS builds: NaN into every position of buffer P (thread tid
+  // takes positions j*BD + BD-1-tid), then a barrier.  A no-op otherwise.
+  // kPoisonBarriers: the barriers it adds to each pass.
+  static constexpr uint32_t kPoisonBarriers = WN_POISON_LDS != 0 ? 1u : 0u;
+  __device__ __forceinline__ void poison(T *P) const {
+    if constexpr (WN_POISON_LDS != 0) {
+      const uint32_t B = bd();
+      for (uint32_t j = 0; j < pool_n() / B; ++j) P[j * B + (B - 1 - tid)] = T(__builtin_nan(""));
+      sync();
+    }
+  }
+
   __device__ __forceinline__ void load_global(const T *__restrict__ g) {
     T *P = cur();
+    poison(P);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -519,6 +541,7 @@ struct Engine {
   // write the registers to the buffer holding the pool
   __device__ __forceinline__ void write_lds() {
     T *P = cur();
+    poison(P);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -622,6 +645,7 @@ struct Engine {
     }
     if (!DB) sync();
     T *W = buf(WB);
+    poison(W);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -748,6 +772,7 @@ struct Engine {
     }
     if (!DB) sync();
     T *W = buf(WB);
+    poison(W);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -1132,6 +1157,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
 
   // Initial values from the top 23 bits of successive uniforms:
   // ((v >> 41) - 2^22 + 1/2) * 2^-22, exact in binary32.
+  e.poison(e.cur());
   if (e.tid == 0) {
     uint64_t xs = stream_seed(a.seed, s);
     for (uint32_t i = 0; i < n; ++i) {
@@ -1385,8 +1411,10 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   for (uint64_t step = 0; !deferred && (PAIR ? step < steps : count > 0); ++step) {
     if (PAIR && count == 0) {
       // this half's item is done: the barriers of one pool step (2 per pass
-      // with one LDS buffer, 1 with two; the last one is the sum of squares')
-      for (uint32_t b = 0; b < (DB ? 1u : 2u) * a.c.R; ++b) __syncthreads();
+      // with one LDS buffer, 1 with two; the last one is the sum of squares'),
+      // plus one per pass in the LDS-poisoning debug build
+      const uint32_t per_pass = (DB ? 1u : 2u) + decltype(e)::kPoisonBarriers;
+      for (uint32_t b = 0; b < per_pass * a.c.R; ++b) __syncthreads();
       continue;
     }
     const bool renorm = k > 0 && K > 0 && k_mod == 0;

@@ -128,6 +128,17 @@ struct FillArgs {
 // The message wn_last_error() returns to the calling thread (wn_api.cpp).
 void set_last_error(const char *msg);
 
+// Enum fields and arguments come from C callers, who may pass any integer:
+// validation reads their object representation as an integer (loading an
+// out-of-range value as the C++ enum type is undefined behaviour).
+template <typename E>
+inline uint32_t enum_bits(const E &e) {
+  static_assert(sizeof(E) == sizeof(uint32_t), "4-byte enums");
+  uint32_t v;
+  __builtin_memcpy(&v, &e, sizeof v);
+  return v;
+}
+
 // wn_fill_stats_noalloc: the statically allocated partials (wn_noalloc.hip).
 // noalloc_partials returns their device address on `device`, which must be the
 // current device; the first call on a device looks it up.

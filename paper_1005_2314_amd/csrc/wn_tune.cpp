@@ -152,6 +152,8 @@ wn_status wn_tune_config(const wn_config *base, const wn_quality_tuning *opts, u
   if (report_cap > 0 && !report) return tune_fail(WN_EINVAL, "%s: report is NULL", who);
   if (nreq == 0 || !streams || !counts || !out)
     return tune_fail(WN_EINVAL, "%s: the timed request is empty or has a NULL array", who);
+  if (wn::enum_bits(out_dtype) > WN_F16)
+    return tune_fail(WN_EINVAL, "%s: unknown output dtype %u", who, wn::enum_bits(out_dtype));
   wn_quality_tuning o;
   std::memset(&o, 0, sizeof(o));
   if (opts) {

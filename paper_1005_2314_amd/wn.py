@@ -10,7 +10,10 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libwn.so")
+# WN_LDS_POISON=1 selects the debug build (every LDS pool write preceded by a
+# NaN fill of the buffer; build.build(poison=True)), for the poisoned parity run.
+LIB_PATH = os.path.join(HERE, "libwn_poison.so" if os.environ.get("WN_LDS_POISON") == "1"
+                        else "libwn.so")
 
 WN_OK, WN_EINVAL, WN_ENOMEM, WN_EDEVICE, WN_ESTATE, WN_ENOTSUP = range(6)
 WN_F64, WN_F32, WN_BF16, WN_F16 = range(4)
