@@ -272,6 +272,7 @@ def other_workloads(W, stream):
         entry[f"{name}_out"] = {"ms": ms, "normals_per_s": o.numel() / ms * 1e3,
                                 "tuning": {"lds_double_buffer": t.lds_double_buffer,
                                            "nontemporal_stores": t.nontemporal_stores,
+                                           "waves_per_simd": t.waves_per_simd,
                                            "streams_per_wg": t.streams_per_wg}}
         del o
     res["precision"] = entry

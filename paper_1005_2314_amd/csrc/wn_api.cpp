@@ -1070,11 +1070,14 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
   // the deferred form is a candidate where it applies (and is otherwise ignored)
   const uint32_t keep_defer = cur.defer_emission;
   if (affine) {
-    // no register caps: on this compiler every cap spills (waves_per_simd stays
-    // a manual choice)
     for (uint32_t spw : {1u, 2u, 4u, 8u})
       for (uint32_t db = 0; db < 2; ++db)
         add(db, 0, 0, cur.wgs_per_cu, cur.long_priority_pct, spw, keep_defer & 2u);
+    // register caps for 5 and 6 waves per SIMD (one LDS buffer): their few
+    // spills sit outside the pool loop, and the extra workgroup per compute
+    // unit pays where the kernel waits on barriers rather than on memory
+    // (16-bit outputs)
+    for (uint32_t oc : {5u, 6u}) add(0, 0, oc, cur.wgs_per_cu, cur.long_priority_pct, 1, keep_defer & 2u);
     add(1, 1, 0, cur.wgs_per_cu, cur.long_priority_pct, 1, keep_defer & 2u);
     if (nreq <= g->cus) add(1, 0, 0, cur.wgs_per_cu, cur.long_priority_pct, 1, keep_defer | 1u);
   } else {
