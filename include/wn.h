@@ -158,6 +158,10 @@ typedef struct {
                                   long-item head run in pairs, one per half of the workgroup
                                   (128 threads each), neighbours in length, in the plain loop
                                   (same results); default 0 */
+  uint32_t threads_per_stream; /* one-size launches of pools of 1024 to 4096 values without
+                                  statistics or rotations: 128 or 256 threads per stream (0 =
+                                  256), the same element layout m*L + c*threads + tid, column
+                                  sums and tree (same results) */
 } wn_tuning;
 
 /* Validate cfg, select the device, allocate the per-stream state in device

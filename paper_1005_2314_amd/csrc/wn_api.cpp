@@ -1000,12 +1000,14 @@ wn_status wn_set_tuning(wn_gen *g, const wn_tuning *t) {
   if (t->lds_double_buffer > 1 || t->nontemporal_stores > 1 || wcode > 3 || t->use_graph > 1 ||
       (wcode && t->nontemporal_stores) || t->wgs_per_cu > 16 || t->long_priority_pct > 100 ||
       t->streams_per_wg < 1 || t->streams_per_wg > 16 || t->defer_emission > 3 ||
-      t->group_items > 1)
+      t->group_items > 1 ||
+      (t->threads_per_stream != 0 && t->threads_per_stream != 128 && t->threads_per_stream != 256))
     return fail(WN_EINVAL, "wn_set_tuning: flags must be 0 or 1, waves_per_simd 0/5/6/8 and "
                            "not with nontemporal_stores, wgs_per_cu <= 16, "
                            "long_priority_pct <= 100, streams_per_wg in [1, 16], "
-                           "defer_emission <= 3");
-  g->variant = t->lds_double_buffer | (t->nontemporal_stores << 1) | (wcode << 2);
+                           "defer_emission <= 3, threads_per_stream 0, 128 or 256");
+  g->variant = t->lds_double_buffer | (t->nontemporal_stores << 1) | (wcode << 2) |
+               (t->threads_per_stream == 128 ? wn::kVariantThreads128 : 0u);
   g->wgs_per_cu = t->wgs_per_cu;
   g->use_graph = t->use_graph != 0;
   g->long_priority_pct = t->long_priority_pct;
@@ -1028,6 +1030,7 @@ wn_status wn_get_tuning(wn_gen *g, wn_tuning *t) {
   t->streams_per_wg = g->streams_per_wg;
   t->defer_emission = g->defer_emission;
   t->group_items = g->group_items;
+  t->threads_per_stream = (g->variant & wn::kVariantThreads128) ? 128u : 256u;
   return WN_OK;
 }
 
@@ -1055,8 +1058,10 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
              g->pool_n[streams[j]] == g->pool_n[streams[0]];
   std::vector<wn_tuning> cands;
   auto add = [&](uint32_t db, uint32_t nt, uint32_t oc, uint32_t wpc, uint32_t prio,
-                 uint32_t spw = 1, uint32_t defer = 0, uint32_t group = 0) {
+                 uint32_t spw = 1, uint32_t defer = 0, uint32_t group = 0,
+                 uint32_t threads = 256) {
     wn_tuning t = cur;
+    t.threads_per_stream = threads;
     t.group_items = group;
     t.defer_emission = defer;
     t.streams_per_wg = spw;
@@ -1078,6 +1083,11 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
     // unit pays where the kernel waits on barriers rather than on memory
     // (16-bit outputs)
     for (uint32_t oc : {5u, 6u}) add(0, 0, oc, cur.wgs_per_cu, cur.long_priority_pct, 1, keep_defer & 2u);
+    // 128 threads per stream for pools of 1024 to 4096 values
+    const uint32_t n0 = nreq > 0 ? g->pool_n[streams[0]] : 0u;
+    if (n0 >= 1024 && n0 <= 4096 && g->transform == 0)
+      for (uint32_t db = 0; db < 2; ++db)
+        add(db, 0, 0, cur.wgs_per_cu, cur.long_priority_pct, 1, keep_defer & 2u, 0, 128);
     add(1, 1, 0, cur.wgs_per_cu, cur.long_priority_pct, 1, keep_defer & 2u);
     if (nreq <= g->cus) add(1, 0, 0, cur.wgs_per_cu, cur.long_priority_pct, 1, keep_defer | 1u);
   } else {

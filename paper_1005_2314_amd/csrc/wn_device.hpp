@@ -431,6 +431,10 @@ __host__ __device__ constexpr size_t sq_scratch_lds(uint32_t n) {
   return nq_of(n) > 1 ? size_t(sq_round(nq_of(n))) * 4 * 64 * sizeof(double) : 0;
 }
 __host__ __device__ constexpr uint32_t slot_set(uint32_t n) { return 4 * nq_of(n); }
+// The LDS layout an item of n values on 128 threads alone uses: that of a
+// 256-thread item of at least 2048 values, whose sum-of-squares scratch and
+// slots cover two columns per thread and per round (n = 1024 has none).
+__host__ __device__ constexpr uint32_t layout_n_128(uint32_t n) { return n < 2048 ? 2048u : n; }
 template <typename T>
 __host__ __device__ constexpr size_t slots_off(uint32_t n, bool db) {
   return pool_lds<T>(n, db) + sq_scratch_lds(n);
@@ -1221,13 +1225,18 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
 //
 // PAIR: the item is half of a pair (128 threads, make_half_engine) and runs
 // the plain loop; nmax is the pool size the LDS is laid out for.
+//
+// BDI = 128 (not PAIR): the item runs on a workgroup of 128 threads alone
+// (NQ = L/128; the same layout and results as 256 threads).
 template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, bool STATS, bool ROT,
-          bool DEFER = false, bool PAIR = false>
+          bool DEFER = false, bool PAIR = false, int BDI = int(kBlock)>
 __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem, uint32_t s,
                                           uint64_t count, uint64_t obase, uint32_t req = 0,
                                           uint32_t nmax = 0) {
   static_assert(!(DEFER && STATS), "the deferred form carries no statistics");
   static_assert(!(PAIR && (STATS || DEFER || SMALL)), "the pair form is the plain loop");
+  static_assert(BDI == int(kBlock) || (BDI == 128 && !PAIR && !SMALL && !STATS && !DEFER),
+                "128-thread items alone: the plain loop without statistics");
   StreamHdr *h = a.c.hdr + s;
   const uint32_t n = uniform32(h->n);
   count = uniform64(count);
@@ -1236,6 +1245,8 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
   auto e = [&]() {
     if constexpr (PAIR)
       return make_half_engine<T, NQ, DB>(smem, n, nmax, half);
+    else if constexpr (BDI == 128)
+      return make_half_engine<T, NQ, DB>(smem, n, layout_n_128(n), 0);
     else
       return make_engine<T, NQ, SMALL, DB>(smem, n);
   }();
@@ -1537,9 +1548,11 @@ __device__ __forceinline__ void fill_item(const FillArgs &a, unsigned char *smem
 // items_per_wg; all items of the launch share one pool size).  In the affine
 // form consecutive items write consecutive output ranges, so a larger P gives
 // each workgroup a longer contiguous run of stores.
+// BDK: threads per workgroup, 256, or 128 for pools of 1024 to 4096 values
+// (NQ = n/512 then; no statistics or rotations).
 template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE, bool STATS,
-          bool ROT>
-__global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
+          bool ROT, int BDK = int(kBlock)>
+__global__ __launch_bounds__(BDK, WPE) void k_fill(FillArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t per = a.items_per_wg;
   bool ran = false;
@@ -1566,7 +1579,8 @@ __global__ __launch_bounds__(kBlock, WPE) void k_fill(FillArgs a) {
     if (ran) __syncthreads();  // the previous item's last LDS reads are done
     ran = true;
     const uint32_t req = a.items ? a.items[j].req : j;
-    fill_item<T, O, NQ, SMALL, DB, NT, STATS, ROT>(a, smem, s, count, obase, req);
+    fill_item<T, O, NQ, SMALL, DB, NT, STATS, ROT, false, false, BDK>(a, smem, s, count, obase,
+                                                                       req);
   }
 }
 

@@ -125,6 +125,10 @@ struct FillArgs {
   StatsOut *stats = nullptr;        // fused statistics: histogram and tails accumulate here
 };
 
+// Launch-variant bit (FillArgs::variant) for 128 threads per stream in
+// one-size launches of pools of 1024 and 2048 values (wn_tuning.threads_per_stream).
+constexpr uint32_t kVariantThreads128 = 16u;
+
 // The message wn_last_error() returns to the calling thread (wn_api.cpp).
 void set_last_error(const char *msg);
 

@@ -59,13 +59,13 @@ hipError_t seed_n(const SeedArgs &a, hipStream_t st) {
 
 // ---- one-size launches --------------------------------------------------------------------
 template <typename T, typename O, int NQ, bool SMALL, bool DB, bool NT, int WPE = 1,
-          bool STATS = false, bool ROT = false>
+          bool STATS = false, bool ROT = false, int BDK = int(kBlock)>
 hipError_t fill_t(const FillArgs &a, hipStream_t st) {
-  const size_t lds = lds_bytes_for<T>(a.c.n, DB, STATS);
-  auto kern = k_fill<T, O, NQ, SMALL, DB, NT, WPE, STATS, ROT>;
+  const size_t lds = lds_bytes_for<T>(BDK == 128 ? layout_n_128(a.c.n) : a.c.n, DB, STATS);
+  auto kern = k_fill<T, O, NQ, SMALL, DB, NT, WPE, STATS, ROT, BDK>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
-  const uint32_t block = SMALL ? a.c.n / 4 : kBlock;
+  const uint32_t block = SMALL ? a.c.n / 4 : uint32_t(BDK);
   const uint32_t per = a.items_per_wg ? a.items_per_wg : 1;
   hipLaunchKernelGGL(kern, dim3((a.nitems + per - 1) / per), dim3(block), lds, st, a);
   return hipGetLastError();
@@ -74,10 +74,19 @@ hipError_t fill_t(const FillArgs &a, hipStream_t st) {
 // Non-semantic variants (identical results).  Binary32 pools of up to 8192
 // values: bit 0 double-buffered LDS, bit 1 nontemporal output stores (with
 // bit 0), bits 2-3 a register cap for 8, 6 or 5 waves per SIMD.  Binary64
-// pools and the plane-rotation family run one variant.
+// pools and the plane-rotation family run one variant.  Bit 4: pools of 1024
+// to 4096 values without statistics or rotations run on 128 threads per
+// stream (with bit 0 as above; the other bits do not apply).
 template <typename T, typename O, int NQ>
 hipError_t fill_v(const FillArgs &a, hipStream_t st) {
   constexpr bool db_fits = kPoolF32<T> && NQ <= 8;
+  if constexpr (NQ <= 4) {
+    if ((a.variant & kVariantThreads128) && !a.c.transform && !a.partials) {
+      if (db_fits && (a.variant & 1u))
+        return fill_t<T, O, 2 * NQ, false, db_fits, false, 1, false, false, 128>(a, st);
+      return fill_t<T, O, 2 * NQ, false, false, false, 1, false, false, 128>(a, st);
+    }
+  }
   if (a.c.transform) {
     if (a.partials) return fill_t<T, O, NQ, false, db_fits, false, 1, true, true>(a, st);
     return fill_t<T, O, NQ, false, db_fits, false, 1, false, true>(a, st);

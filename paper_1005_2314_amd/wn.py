@@ -58,7 +58,8 @@ class wn_tuning(C.Structure):
                 ("nontemporal_stores", C.c_uint32), ("waves_per_simd", C.c_uint32),
                 ("wgs_per_cu", C.c_uint32), ("use_graph", C.c_uint32),
                 ("long_priority_pct", C.c_uint32), ("streams_per_wg", C.c_uint32),
-                ("defer_emission", C.c_uint32), ("group_items", C.c_uint32)]
+                ("defer_emission", C.c_uint32), ("group_items", C.c_uint32),
+                ("threads_per_stream", C.c_uint32)]
 
 
 HIST_BINS = 4096
@@ -412,8 +413,10 @@ class Generator:
 
     def set_tuning(self, lds_double_buffer=None, nontemporal_stores=None, waves_per_simd=None,
                    wgs_per_cu=None, use_graph=None, long_priority_pct=None, streams_per_wg=None,
-                   defer_emission=None, group_items=None):
+                   defer_emission=None, group_items=None, threads_per_stream=None):
         t = self.tuning()
+        if threads_per_stream is not None:
+            t.threads_per_stream = int(threads_per_stream)
         if group_items is not None:
             t.group_items = int(group_items)
         if defer_emission is not None:

@@ -194,11 +194,35 @@ def test_streams_per_workgroup_bit_exact(spw, n, db):
     assert g.size == 0
 
 
+@pytest.mark.parametrize("n,pool,out,db", [(1024, "f32", W.WN_F32, 0), (1024, "f32", W.WN_BF16, 1),
+                                         (2048, "f32", W.WN_F16, 0), (2048, "f32", W.WN_F32, 1),
+                                         (1024, "f64", W.WN_F64, 0), (2048, "f64", W.WN_F32, 0),
+                                         (4096, "f32", W.WN_BF16, 0), (4096, "f32", W.WN_F32, 1)])
+def test_128_threads_per_stream_bit_exact(n, pool, out, db):
+    # the same element layout on 128 threads (NQ = L/128): identical bits and
+    # state, with continuing calls of ragged lengths and a later change of form
+    ns = 7
+    p = Pair(ns, pool_n=n, R=2, pool=pool, seed=31)
+    p.gpu.set_tuning(threads_per_stream=128, lds_double_buffer=db, defer_emission=0)
+    assert p.gpu.tuning().threads_per_stream == 128
+    for per in (3 * (n - 1) + 5, 1, n - 2, 17 * n + 3):
+        g, o = p.fill(np.arange(ns), [per] * ns, out)
+        assert_bits_equal(g, o, f"128 threads, {per} per stream")
+    p.gpu.set_tuning(threads_per_stream=256)
+    g, o = p.fill(np.arange(ns), [2 * n] * ns, out)
+    assert_bits_equal(g, o, "back to 256 threads")
+    for s in (0, 6):
+        gi, gp = p.gpu.stream_state(s)
+        oi, op = p.orc.stream(s)
+        assert_bits_equal(bits(gp), bits(op), f"pool of stream {s}")
+
+
 def test_tuning_rejects_bad_values():
     g = W.Generator(2, pool_n=64, R=1)
     for field, value in (("lds_double_buffer", 2), ("long_priority_pct", 101),
                          ("waves_per_simd", 7), ("wgs_per_cu", 17), ("streams_per_wg", 0),
-                         ("streams_per_wg", 17)):
+                         ("streams_per_wg", 17), ("threads_per_stream", 64),
+                         ("threads_per_stream", 512)):
         t = g.tuning()
         setattr(t, field, value)
         with pytest.raises(W.WnError) as ei:
