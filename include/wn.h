@@ -158,10 +158,12 @@ typedef struct {
                                   long-item head run in pairs, one per half of the workgroup
                                   (128 threads each), neighbours in length, in the plain loop
                                   (same results); default 0 */
-  uint32_t threads_per_stream; /* one-size launches of pools of 1024 to 4096 values without
-                                  statistics or rotations: 128 or 256 threads per stream (0 =
-                                  256), the same element layout m*L + c*threads + tid, column
-                                  sums and tree (same results) */
+  uint32_t threads_per_stream; /* without statistics, rotations, thinning or exponential
+                                  variates: 128 or 256 threads per stream (0 = 256) in one-size
+                                  launches of pools of 1024 to 4096 values and in persistent
+                                  launches whose pools hold at most 2048; the same element
+                                  layout m*L + c*threads + tid, column sums and tree (same
+                                  results) */
 } wn_tuning;
 
 /* Validate cfg, select the device, allocate the per-stream state in device

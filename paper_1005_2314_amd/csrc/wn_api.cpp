@@ -1097,6 +1097,13 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
           for (uint32_t wpc : {0u, 3u, 4u, 6u})
             add(db, 0, 0, wpc, prio, 1, keep_defer & 1u, group);
     add(1, 1, 0, 0, 25, 1, keep_defer & 1u);
+    // 128 threads per item where every pool holds at most 2048 values
+    uint32_t max_n = 0;
+    for (uint32_t j = 0; j < nreq; ++j) max_n = std::max(max_n, g->pool_n[streams[j]]);
+    if (max_n >= 1024 && max_n <= 2048 && g->transform == 0 && g->stride == 1)
+      for (uint32_t prio : {0u, 25u})
+        for (uint32_t db = 0; db < 2; ++db)
+          for (uint32_t wpc : {0u, 4u, 8u}) add(db, 0, 0, wpc, prio, 1, keep_defer & 1u, 0, 128);
     for (uint32_t group = 0; group < 2; ++group)
       for (uint32_t prio : {0u, 25u, 50u})
         for (uint32_t wpc : {0u, 2u, 3u, 4u}) add(1, 0, 0, wpc, prio, 1, keep_defer | 2u, group);

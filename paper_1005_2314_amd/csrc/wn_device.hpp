@@ -1678,6 +1678,37 @@ __global__ __launch_bounds__(kBlock, PAIRS ? 4 : 1) void k_fill_persistent(FillA
   }
 }
 
+// Persistent form on 128-thread workgroups, for lists whose pools hold 1024 or
+// 2048 values (no statistics, rotations or deferred emission): each item runs
+// alone on 128 threads (NQ = n/512) with the layout of a 2048-value item, so
+// the results are those of every other form.  The item word is misc word 3 of
+// that layout, which no item uses.
+template <typename T, typename O, bool DB, bool NT>
+__global__ __launch_bounds__(128) void k_fill_persistent128(FillArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t &next_item =
+      *reinterpret_cast<uint64_t *>(smem + lds_bytes_for<T>(2048, DB, false) - sizeof(uint64_t));
+  for (;;) {
+    __syncthreads();  // the previous item's last LDS reads are done
+    if (threadIdx.x == 0) next_item = atomicAdd(a.counter, 1u);
+    __syncthreads();
+    const uint32_t j = uint32_t(next_item);
+    if (j >= a.nitems) break;
+    if (j < a.prio_items)
+      __builtin_amdgcn_s_setprio(3);
+    else
+      __builtin_amdgcn_s_setprio(0);
+    const WorkItem it = a.items[j];
+    if (it.count == 0) continue;
+    if (a.c.hdr[it.stream].n == 1024)
+      fill_item<T, O, 2, false, DB, NT, false, false, false, false, 128>(a, smem, it.stream,
+                                                                         it.count, it.out_off, it.req);
+    else
+      fill_item<T, O, 4, false, DB, NT, false, false, false, false, 128>(a, smem, it.stream,
+                                                                         it.count, it.out_off, it.req);
+  }
+}
+
 [[maybe_unused]] __global__ void k_reset_counter(uint32_t *ctr) {
   if (threadIdx.x == 0) *ctr = 0u;
 }

@@ -75,13 +75,15 @@ hipError_t fill_t(const FillArgs &a, hipStream_t st) {
 // values: bit 0 double-buffered LDS, bit 1 nontemporal output stores (with
 // bit 0), bits 2-3 a register cap for 8, 6 or 5 waves per SIMD.  Binary64
 // pools and the plane-rotation family run one variant.  Bit 4: pools of 1024
-// to 4096 values without statistics or rotations run on 128 threads per
-// stream (with bit 0 as above; the other bits do not apply).
+// to 4096 values without statistics, rotations, thinning or exponential
+// variates run on 128 threads per stream (with bit 0 as above; the other bits
+// do not apply).
 template <typename T, typename O, int NQ>
 hipError_t fill_v(const FillArgs &a, hipStream_t st) {
   constexpr bool db_fits = kPoolF32<T> && NQ <= 8;
   if constexpr (NQ <= 4) {
-    if ((a.variant & kVariantThreads128) && !a.c.transform && !a.partials) {
+    if ((a.variant & kVariantThreads128) && !a.c.transform && !a.partials && a.c.stride == 1 &&
+        !a.c.expo) {
       if (db_fits && (a.variant & 1u))
         return fill_t<T, O, 2 * NQ, false, db_fits, false, 1, false, false, 128>(a, st);
       return fill_t<T, O, 2 * NQ, false, false, false, 1, false, false, 128>(a, st);
@@ -187,6 +189,30 @@ hipError_t persistent_t(const FillArgs &a, uint32_t grid, hipStream_t st) {
   return hipGetLastError();
 }
 
+// 128 threads per item (variant bit kVariantThreads128), pools of 1024 and 2048.
+template <typename T, typename O, bool DB, bool NT>
+hipError_t persistent128_t(const FillArgs &a, uint32_t grid, hipStream_t st) {
+  const size_t lds = lds_bytes_for<T>(2048, DB, false);
+  auto kern = k_fill_persistent128<T, O, DB, NT>;
+  hipError_t e = prepare(kern, lds);
+  if (e != hipSuccess) return e;
+  if (grid == 0) {  // as many workgroups as can be resident at once
+    int per_cu = 0, dev = 0, cus = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 128, lds)) !=
+            hipSuccess ||
+        (e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+            hipSuccess)
+      return e;
+    grid = uint32_t(cus) * uint32_t(per_cu > 0 ? per_cu : 1);
+  }
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, a.counter);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(128), lds, st, a);
+  return hipGetLastError();
+}
+
 // Binary32 pools: bit 0 double-buffered LDS, bit 1 nontemporal stores (with
 // two buffers).  Binary64 pools: two buffers only where they fit in LDS.
 template <typename T, typename O, int MAXNQ>
@@ -232,6 +258,11 @@ hipError_t persistent_n(const FillArgs &a, uint32_t max_n, uint32_t grid, hipStr
   if (defer_applies(a, max_n, 4096))  // two LDS buffers of the largest pool fit for both types
     return a.c.transform ? persistent_t<T, O, 4, true, false, false, true, true>(a, grid, st)
                          : persistent_t<T, O, 4, true, false, false, false, true>(a, grid, st);
+  if ((a.variant & kVariantThreads128) && max_n <= 2048 && !a.partials && !a.c.transform &&
+      a.c.stride == 1 && !a.c.expo) {
+    if (kPoolF32<T> && (a.variant & 1u)) return persistent128_t<T, O, kPoolF32<T>, false>(a, grid, st);
+    return persistent128_t<T, O, false, false>(a, grid, st);
+  }
   if (max_n <= 4096) return persistent_v<T, O, 4>(a, grid, st);
   return persistent_v<T, O, 16>(a, grid, st);
 }

@@ -359,3 +359,22 @@ def test_output_offsets_beyond_2_31(mixed):
         assert_bits_equal(got, want[i * per:(i + 1) * per], f"stream {s} at offset {j * per}")
     del y
     g.close()
+
+
+@pytest.mark.parametrize("db,wpc", [(0, 0), (1, 8), (0, 4)])
+def test_persistent_128_threads_bit_exact(db, wpc):
+    # persistent launches on 128-thread workgroups (pools of 1024 and 2048):
+    # the same bits as the oracle across calls and after switching back
+    sizes = np.array([1024, 2048] * 9, np.uint32)
+    p = Pair(len(sizes), pool_n=sizes, R=2, seed=57)
+    p.gpu.set_tuning(threads_per_stream=128, lds_double_buffer=db, wgs_per_cu=wpc,
+                     long_priority_pct=25)
+    rng = np.random.default_rng(wpc + db)
+    for call in range(3):
+        order, counts = _request(rng, len(sizes), 40000)
+        g, o = p.fill(order, counts, W.WN_F32 if call != 1 else W.WN_BF16)
+        assert_bits_equal(g, o, f"128-thread persistent, call {call}")
+    p.gpu.set_tuning(threads_per_stream=256)
+    order, counts = _request(rng, len(sizes), 20000)
+    g, o = p.fill(order, counts)
+    assert_bits_equal(g, o, "back to 256 threads")
