@@ -979,7 +979,7 @@ struct Engine {
         return;
       }
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 4; ++m) {
 #pragma unroll
         for (int c = 0; c < NQ; ++c) {
           const O v = Cast<O>::from(scaled<MU>(y[c][m], fT, muT));
@@ -988,6 +988,11 @@ struct Engine {
             if constexpr (STATS) sa->add(widen(v));
           }
         }
+        // with statistics, one row's values at a time: the scheduler would
+        // otherwise keep every value's binary64 conversion in flight, and the
+        // registers would not fit four workgroups per compute unit
+        if constexpr (STATS) __builtin_amdgcn_sched_barrier(0);
+      }
       return;
     }
 #pragma unroll

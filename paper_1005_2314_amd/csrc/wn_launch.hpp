@@ -96,7 +96,7 @@ hipError_t fill_v(const FillArgs &a, hipStream_t st) {
   if (a.partials) {  // statistics: one LDS buffer unless bit 0 asks for two
     if constexpr (db_fits)
       if (a.variant & 1u) return fill_t<T, O, NQ, false, true, false, 1, true>(a, st);
-    return fill_t<T, O, NQ, false, false, false, 1, true>(a, st);
+    return fill_t<T, O, NQ, false, false, false, 4, true>(a, st);
   }
   if constexpr (db_fits) {
     const bool db = a.variant & 1u;
