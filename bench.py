@@ -263,8 +263,8 @@ def other_workloads(W, stream):
     q = inputs.precision()
     g = W.Generator(q["num_streams"], pool_n=q["pool_n"], R=q["R"])
     g.seed(q["seed"])
-    entry = {"config": "16384 streams x 2^16, pool 4096 binary32, R=2; launch choices by the "
-                       "autotuner per output type"}
+    entry = {"config": "16384 streams x 2^16, pool 4096 binary32 (and binary64: f64_pool_*), R=2; "
+                       "launch choices by the autotuner per output type"}
     for dt, name in ((W.WN_BF16, "bf16"), (W.WN_F16, "f16"), (W.WN_F32, "f32")):
         o = torch.empty(int(q["counts"].sum()), dtype=W.torch_dtype(dt), device="cuda")
         t = g.autotune(o, q["streams"], q["counts"], stream)
@@ -274,6 +274,18 @@ def other_workloads(W, stream):
                                            "nontemporal_stores": t.nontemporal_stores,
                                            "waves_per_simd": t.waves_per_simd,
                                            "streams_per_wg": t.streams_per_wg}}
+        del o
+    g.close()
+    # the same workload from binary64 pools
+    g = W.Generator(q["num_streams"], pool_n=q["pool_n"], R=q["R"], pool_dtype=W.WN_F64)
+    g.seed(q["seed"])
+    for dt, name in ((W.WN_F64, "f64"), (W.WN_F32, "f32"), (W.WN_BF16, "bf16")):
+        o = torch.empty(int(q["counts"].sum()), dtype=W.torch_dtype(dt), device="cuda")
+        t = g.autotune(o, q["streams"], q["counts"], stream)
+        ms = steady(lambda: g.fill_into(o, q["streams"], q["counts"], stream))
+        entry[f"f64_pool_{name}_out"] = {"ms": ms, "normals_per_s": o.numel() / ms * 1e3,
+                                         "tuning": {"lds_double_buffer": t.lds_double_buffer,
+                                                    "threads_per_stream": t.threads_per_stream}}
         del o
     res["precision"] = entry
     g.close()
