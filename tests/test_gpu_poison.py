@@ -36,6 +36,9 @@ cases = [
     ([64, 1024, 256, 4096, 16, 2048, 16384, 512, 1024, 1024, 2048, 4096], 2, "f32", W.WN_F32,
      {{"defer_emission": 3, "lds_double_buffer": 1}}, 0),
     ([1024] * 10 + [2048, 4096], 2, "f32", W.WN_F32, {{"group_items": 1}}, 0),
+    (1024, 2, "f32", W.WN_BF16, {{"threads_per_stream": 128}}, 0),
+    (2048, 2, "f64", W.WN_F32, {{"threads_per_stream": 128, "lds_double_buffer": 1}}, 0),
+    ([1024, 2048] * 6, 2, "f32", W.WN_F32, {{"threads_per_stream": 128, "wgs_per_cu": 4}}, 0),
 ]
 for i, (sizes, R, pool, out, tune, rot) in enumerate(cases):
     print("poisoned case", i, flush=True)
