@@ -326,35 +326,39 @@ def test_uneven_batch_full_size_sampled():
         at += c
 
 
+@pytest.mark.parametrize("bit", [31, 32])
 @pytest.mark.parametrize("mixed", [False, True])
-def test_output_offsets_beyond_2_31(mixed):
+def test_output_offsets_beyond_2_31(mixed, bit):
     """Outputs at element offsets of 2^31 and more (bit 31 of the offset's low
-    word set), in a one-size launch and in a work-list launch: the streams at
-    and after the 2^31 boundary equal the oracle's."""
+    word set) and of 2^32 and more (a nonzero high word), in a one-size launch
+    and in a work-list launch: the streams at and after the boundary equal the
+    oracle's."""
     import torch
     from gpu_util import to_numpy_bits
     from oracle import oracle as O
-    ns, per = 36864, 1 << 16  # 2.4e9 binary16-sized outputs
+    per = 1 << 16
+    edge = (1 << bit) // per  # the request whose output starts at 2^bit
+    ns = edge + 4096  # 2.4e9 or 4.6e9 binary16-sized outputs
     sizes = (np.where(np.arange(ns) % 2 == 0, 1024, 4096).astype(np.uint32) if mixed
              else np.full(ns, 4096, np.uint32))
     g = W.Generator(ns, pool_n=sizes, R=2)
     g.seed(77)
     streams = np.arange(ns, dtype=np.uint32)[::-1].copy() if mixed else np.arange(ns,
                                                                                  dtype=np.uint32)
-    print(f"offsets beyond 2^31, mixed={mixed}", flush=True)
+    print(f"offsets beyond 2^{bit}, mixed={mixed}", flush=True)
     y = g.fill(streams, np.full(ns, per, np.uint64), W.WN_BF16)
     torch.cuda.synchronize()
     g.sync()
     pos = {int(s): j for j, s in enumerate(streams)}
-    # the requests whose outputs start just before, at and after 2^31, and the last
-    picks = sorted({32767, 32768, 32769, ns - 1})
+    # the requests whose outputs start just before, at and after 2^bit, and the last
+    picks = sorted({edge - 1, edge, edge + 1, ns - 1})
     chosen = [int(streams[j]) for j in picks]
     orc = O.Generator(ns, pool_n=sizes, R=2)
     orc.seed(77)
     want = orc.fill(chosen, [per] * len(chosen), O.BF16)
     for i, s in enumerate(chosen):
         j = pos[s]
-        assert j * per >= (1 << 31) - per
+        assert j * per >= (1 << bit) - per
         got = to_numpy_bits(y[j * per:(j + 1) * per])
         assert_bits_equal(got, want[i * per:(i + 1) * per], f"stream {s} at offset {j * per}")
     del y
