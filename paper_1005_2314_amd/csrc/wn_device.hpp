@@ -560,27 +560,60 @@ struct Engine {
       for (int c = 0; c < NQ; ++c) y[c][m] = T(__dmul_rn(double(y[c][m]), g));
   }
 
-  // Gather quadruples from buffer RB and transform them with matrix K.  The
-  // row position is (alpha q + gamma) mod L for q = c*BD + tid: one add to
-  // step c and one mask per element; row and buffer offsets are immediates.
+  // Byte offsets within row m of the gathers of columns q = c*BD + tid: the
+  // row position (alpha_m q + gamma_m) mod L, one add to step c and one mask
+  // per element.  alpha_m is odd, so the columns c and c + NQ/2 read positions
+  // L/2 apart (mod L): the second half of the offsets is the first half with
+  // the top bit of the row offset flipped, one XOR each.
+  __device__ __forceinline__ void quad_offsets(const PassParams &p, int m,
+                                               uint32_t (&ad)[NQ]) const {
+    const uint32_t L = len();
+    constexpr uint32_t W = sizeof(T);
+    const uint32_t mask = (L - 1) * W;
+    const uint32_t a = p.alpha[m];
+    const uint32_t first = __umul24(a * W, tid) + p.gamma[m] * W;
+    const uint32_t step = a * bd() * W;
+#pragma unroll
+    for (int c = 0; c < NQ; ++c)
+      ad[c] = (NQ >= 2 && c >= NQ / 2) ? (ad[c - NQ / 2] ^ (L * W / 2))
+                                       : ((first + step * uint32_t(c)) & mask);
+  }
+
+  // Byte offsets within row r (of H = 2L) of the gathers of pairs
+  // q = h*L + c*BD + tid: ad[h][c] for the position (alpha_r q + gamma_r) mod H.
+  // alpha_r is odd, so h = 1 reads L positions (half the row) from h = 0: the
+  // top bit of the offset flipped.
+  __device__ __forceinline__ void pair_offsets(const PassParams &p, int r,
+                                               uint32_t (&ad)[2][NQ]) const {
+    const uint32_t L = len();
+    constexpr uint32_t W = sizeof(T);
+    const uint32_t mask = (2 * L - 1) * W;
+    const uint32_t a = p.alpha[r];
+    const uint32_t first = __umul24(a * W, tid) + p.gamma[r] * W;
+    const uint32_t step = a * bd() * W;
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) {
+      ad[0][c] = (first + step * uint32_t(c)) & mask;
+      ad[1][c] = ad[0][c] ^ (L * W);
+    }
+  }
+
+  // Gather quadruples from buffer RB and transform them with matrix K; row
+  // and buffer offsets are immediates.
   // RN: apply the renormalisation scale g to every gathered value first.
   template <int K, int RB, bool RN>
   __device__ __forceinline__ void gather_transform(const PassParams &p, double g) {
     LdsT *P = lds_buf(RB);
     const uint32_t L = len();
-    constexpr uint32_t W = sizeof(T);
-    const uint32_t mask = (L - 1) * W;  // byte offsets within a row
     using LdsB = __attribute__((address_space(3))) const unsigned char;
     T x[NQ][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const uint32_t a = p.alpha[m];
-      const uint32_t first = __umul24(a * W, tid) + p.gamma[m] * W;
-      const uint32_t step = a * bd() * W;
+      uint32_t ad[NQ];
+      quad_offsets(p, m, ad);
       LdsB *row = reinterpret_cast<LdsB *>(P + uint32_t(m) * L);
 #pragma unroll
-      for (int c = 0; c < NQ; ++c)
-        x[c][m] = *reinterpret_cast<LdsT *>(row + ((first + step * uint32_t(c)) & mask));
+      for (int c = 0; c < NQ; ++c) x[c][m] = *reinterpret_cast<LdsT *>(row + ad[c]);
     }
     if constexpr (RN) {
 #pragma unroll
@@ -600,24 +633,18 @@ struct Engine {
   template <int RB, bool RN>
   __device__ __forceinline__ void gather_rotate(const PassParams &p, double g) {
     LdsT *P = lds_buf(RB);
-    const uint32_t L = len();
-    const uint32_t H = 2 * L;
-    constexpr uint32_t W = sizeof(T);
-    const uint32_t mask = (H - 1) * W;
+    const uint32_t H = 2 * len();
     using LdsB = __attribute__((address_space(3))) const unsigned char;
     T x[NQ][4];  // x[c][h + 2r]: row r's operand of pair h*L + c*BD + tid
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      const uint32_t a = p.alpha[r];
-      const uint32_t step = a * bd() * W;
+      uint32_t ad[2][NQ];
+      pair_offsets(p, r, ad);
       LdsB *row = reinterpret_cast<LdsB *>(P + uint32_t(r) * H);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const uint32_t first = __umul24(a * W, tid) + p.gamma[r] * W + a * (uint32_t(h) * L) * W;
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int c = 0; c < NQ; ++c)
-          x[c][h + 2 * r] = *reinterpret_cast<LdsT *>(row + ((first + step * uint32_t(c)) & mask));
-      }
+        for (int c = 0; c < NQ; ++c) x[c][h + 2 * r] = *reinterpret_cast<LdsT *>(row + ad[h][c]);
     }
     if constexpr (RN) {
 #pragma unroll
@@ -682,47 +709,36 @@ struct Engine {
 
   // The gathers of gather_transform (quadruples) and gather_rotate (pairs,
   // x[c][h + 2r] = row r's operand of pair h*L + c*BD + tid) on their own, for
-  // pass_finish_from; the plain passes keep their fused forms, whose address
-  // arithmetic the compiler folds better.
+  // pass_finish_from (the plain passes fuse them with the transform).
   template <int RB>
   __device__ __forceinline__ void load_quads(const PassParams &p, T (&x)[NQ][4]) const {
     LdsT *P = lds_buf(RB);
     const uint32_t L = len();
-    constexpr uint32_t W = sizeof(T);
-    const uint32_t mask = (L - 1) * W;  // byte offsets within a row
+    using LdsB = __attribute__((address_space(3))) const unsigned char;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const uint32_t a = p.alpha[m];
-      const uint32_t first = __umul24(a * W, tid) + p.gamma[m] * W;
-      const uint32_t step = a * bd() * W;
-      using LdsB = __attribute__((address_space(3))) const unsigned char;
+      uint32_t ad[NQ];
+      quad_offsets(p, m, ad);
       LdsB *row = reinterpret_cast<LdsB *>(P + uint32_t(m) * L);
 #pragma unroll
-      for (int c = 0; c < NQ; ++c)
-        x[c][m] = *reinterpret_cast<LdsT *>(row + ((first + step * uint32_t(c)) & mask));
+      for (int c = 0; c < NQ; ++c) x[c][m] = *reinterpret_cast<LdsT *>(row + ad[c]);
     }
   }
 
   template <int RB>
   __device__ __forceinline__ void load_pairs(const PassParams &p, T (&x)[NQ][4]) const {
     LdsT *P = lds_buf(RB);
-    const uint32_t L = len();
-    const uint32_t H = 2 * L;
-    constexpr uint32_t W = sizeof(T);
-    const uint32_t mask = (H - 1) * W;
+    const uint32_t H = 2 * len();
     using LdsB = __attribute__((address_space(3))) const unsigned char;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      const uint32_t a = p.alpha[r];
-      const uint32_t step = a * bd() * W;
+      uint32_t ad[2][NQ];
+      pair_offsets(p, r, ad);
       LdsB *row = reinterpret_cast<LdsB *>(P + uint32_t(r) * H);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const uint32_t first = __umul24(a * W, tid) + p.gamma[r] * W + a * (uint32_t(h) * L) * W;
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int c = 0; c < NQ; ++c)
-          x[c][h + 2 * r] = *reinterpret_cast<LdsT *>(row + ((first + step * uint32_t(c)) & mask));
-      }
+        for (int c = 0; c < NQ; ++c) x[c][h + 2 * r] = *reinterpret_cast<LdsT *>(row + ad[h][c]);
     }
   }
 
@@ -958,8 +974,23 @@ struct Engine {
                                        uint32_t hi, T fT, StatsAcc *sa, T muT) const {
     const uint32_t L = len();
     if (lo == 0 && hi == 4 * L - 1) {
-      // a whole pool: every position but the withheld last one
-      O *dst = out + obase + tid;
+      // a whole pool: every position but the withheld last one.  Each row's
+      // base is wave-uniform (scalar registers) and the lane's byte offset
+      // one 32-bit register, so the stores take the scalar-base form with
+      // the column offsets as immediates
+      unsigned char *const ob = reinterpret_cast<unsigned char *>(out + obase);
+      uint32_t row[4];
+      // each row's byte offset for this lane, kept as it is in a 32-bit
+      // register (else the compiler folds it into a per-lane 64-bit base and
+      // adds the row offsets to that with vector instructions)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        row[m] = (uint32_t(m) * L + tid) * uint32_t(sizeof(O));
+        asm("" : "+v"(row[m]));
+      }
+      auto dst = [&](int m, int c) {
+        return reinterpret_cast<O *>(ob + uint64_t(row[m]) + uint64_t(uint32_t(c) * bd()) * sizeof(O));
+      };
       if constexpr (sizeof(O) == 2 && NQ % 2 == 0) {
         // 16-bit outputs: columns c and c+1 converted together
 #pragma unroll
@@ -969,10 +1000,10 @@ struct Engine {
             const uint32_t pk = Cast2<O>::from(float(scaled<MU>(y[c][m], fT, muT)),
                                                float(scaled<MU>(y[c + 1][m], fT, muT)));
             const O v0{uint16_t(pk)}, v1{uint16_t(pk >> 16)};
-            put<NT>(dst + (uint32_t(m) * L + uint32_t(c) * bd()), v0);
+            put<NT>(dst(m, c), v0);
             if constexpr (STATS) sa->add(widen(v0));
             if (m < 3 || c + 1 < NQ - 1 || tid < bd() - 1) {
-              put<NT>(dst + (uint32_t(m) * L + uint32_t(c + 1) * bd()), v1);
+              put<NT>(dst(m, c + 1), v1);
               if constexpr (STATS) sa->add(widen(v1));
             }
           }
@@ -984,7 +1015,7 @@ struct Engine {
         for (int c = 0; c < NQ; ++c) {
           const O v = Cast<O>::from(scaled<MU>(y[c][m], fT, muT));
           if (m < 3 || c < NQ - 1 || tid < bd() - 1) {
-            put<NT>(dst + (uint32_t(m) * L + uint32_t(c) * bd()), v);
+            put<NT>(dst(m, c), v);
             if constexpr (STATS) sa->add(widen(v));
           }
         }
