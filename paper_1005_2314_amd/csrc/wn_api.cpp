@@ -1186,16 +1186,20 @@ wn_status wn_autotune(wn_gen *g, uint32_t nreq, const uint32_t *streams, const u
       if ((r = time_once(cands[first[f].second], &ms)) != WN_OK) return give_up(r);
       runs[f].push_back(ms);
     }
+  // Finalists within 1% of the best median are ties: the one earliest in the
+  // candidate list wins (the list starts with the defaults), so that launch
+  // variants equal within noise do not alternate from one run to the next.
+  std::vector<float> med(nfinal);
   float best_ms = 1e30f;
-  wn_tuning chosen = cur;
   for (size_t f = 0; f < nfinal; ++f) {
     std::sort(runs[f].begin(), runs[f].end());
-    const float med = runs[f][runs[f].size() / 2];
-    if (med < best_ms) {
-      best_ms = med;
-      chosen = cands[first[f].second];
-    }
+    med[f] = runs[f][runs[f].size() / 2];
+    best_ms = std::min(best_ms, med[f]);
   }
+  size_t pick = cands.size();
+  for (size_t f = 0; f < nfinal; ++f)
+    if (med[f] <= best_ms * 1.01f) pick = std::min(pick, first[f].second);
+  const wn_tuning chosen = cands[pick];
   wn_set_tuning(g, &chosen);
   cleanup();
   if ((e = record_last(g, st)) != hipSuccess) return hip_fail(e, "wn_autotune: event");
