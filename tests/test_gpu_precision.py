@@ -8,7 +8,9 @@ Bounds: a binary64 pool cast to the output type is the reference rounded once
 more (bf16/f16 through binary32: at most one ulp of the output type); a
 binary32 pool adds the binary32 rounding walk of the passes, bounded as in the
 oracle's own test (8 sqrt(P) 2^-24 on values of unit size, P = passes since
-seeding), plus the output rounding.  The measured errors are written to
+seeding: the walk's standard deviation is below sqrt(P) 2^-24, and the largest
+of the 4e5 values compared stays under 8.3 standard deviations except with
+probability 1e-9), plus the output rounding.  The measured errors are written to
 precision.json in the directory named by WN_REPORT_DIR, when it is set.
 """
 import json

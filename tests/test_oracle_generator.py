@@ -258,13 +258,36 @@ def test_binary32_pool_tracks_binary64_pool():
     # The passes are orthogonal, so binary32 rounding errors (about 2^-24 per
     # operation on values of unit size) add up like a random walk over the
     # P passes since seeding; the output rounding adds half an ulp:
-    #   |y32 - y64| <= ulp32(y)/2 + c sqrt(P) 2^-24,
-    # with c = 8 (about 2.4 times the largest ratio seen on the CPU at
-    # n = 4096, R = 2 over 1 to 100 pools).
+    #   |y32 - y64| <= ulp32(y)/2 + c sqrt(P) 2^-24.
+    # The walk's standard deviation is s sqrt(P) 2^-24 with s below 1 (pinned
+    # by test_binary32_walk_scale), and the largest of M errors stays below
+    # s sqrt(P) 2^-24 sqrt(2 ln(2M / delta)) except with probability delta:
+    # for M = 4e5 values and delta = 1e-9, c = 8 covers s up to 0.97.
     P = int(math.log2(n)) + 4 + 2 * pools
     ulp = np.spacing(np.abs(y64).astype(np.float32)).astype(np.float64)
     assert np.all(err <= 0.5 * ulp + 8.0 * math.sqrt(P) * 2.0**-24)
     assert np.max(err) > 0  # the two precisions do differ
+
+
+@pytest.mark.parametrize("pools", [1, 10, 40, 100])
+def test_binary32_walk_scale(pools):
+    # The model behind the precision bound: each output of a pass carries three
+    # or four roundings of values of unit size (within half an ulp each), and
+    # the orthogonal passes carry earlier errors without growing them, so after
+    # P passes the binary32 pool's error against the binary64 pool has a
+    # standard deviation of s sqrt(P) 2^-24 with s of order one, the same at
+    # every P (the sqrt(P) law); its largest value over a pool is a Gaussian
+    # maximum, not a heavier tail.
+    n = 4096
+    g32 = gen(n, R=2, pool="f32", streams=2)
+    g64 = gen(n, R=2, pool="f64", streams=2)
+    N = pools * (n - 1)
+    e = (g32.fill([1], [N]).astype(np.float64) - g64.fill([1], [N], O.F64))[-(n - 1):]
+    P = int(math.log2(n)) + 4 + 2 * pools
+    unit = math.sqrt(P) * 2.0**-24
+    rms = math.sqrt(float(np.mean(e * e)))
+    assert 0.6 < rms / unit < 1.0, rms / unit
+    assert np.max(np.abs(e)) <= rms * math.sqrt(2 * math.log(2 * (n - 1) / 1e-6))
 
 
 def test_renormalisation_holds_the_norm():
