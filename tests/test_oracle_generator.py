@@ -262,7 +262,7 @@ def test_binary32_pool_tracks_binary64_pool():
     # The walk's standard deviation is s sqrt(P) 2^-24 with s below 1 (pinned
     # by test_binary32_walk_scale), and the largest of M errors stays below
     # s sqrt(P) 2^-24 sqrt(2 ln(2M / delta)) except with probability delta:
-    # for M = 4e5 values and delta = 1e-9, c = 8 covers s up to 0.97.
+    # for M = 4e5 values and delta = 1e-9, c = 8 covers s up to 0.96.
     P = int(math.log2(n)) + 4 + 2 * pools
     ulp = np.spacing(np.abs(y64).astype(np.float32)).astype(np.float64)
     assert np.all(err <= 0.5 * ulp + 8.0 * math.sqrt(P) * 2.0**-24)
