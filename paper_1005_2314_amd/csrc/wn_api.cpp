@@ -666,6 +666,9 @@ wn_status enqueue_fill(wn_gen *g, uint32_t nreq, const uint32_t *streams, const 
     off[j] = acc;
     acc += counts[j];
   }
+  // Pools of 1024 values or more go to the persistent launch, smaller ones to
+  // one-size launches per pool size: a persistent work list never holds a pool
+  // below 1024 (its 128-thread form relies on that for lists up to 2048).
   uint32_t nbig = 0, nsmall = 0, max_n = 1024;
   for (uint32_t j = 0; j < nreq; ++j) {
     if (counts[j] == 0) continue;
