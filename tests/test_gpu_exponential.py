@@ -153,3 +153,52 @@ def test_rejections():
     b, o = p.fill([0, 1], [100, 200])
     assert_bits_equal(a, o, "after refused calls")
     g.close()
+
+
+@pytest.mark.parametrize("n,pool,out", [(64, "f32", W.WN_F32), (1024, "f64", W.WN_F32),
+                                        (4096, "f32", W.WN_BF16), (16384, "f64", W.WN_F64)])
+def test_rotation_family_bit_exact(n, pool, out):
+    """Exponential variates from pools renewed by plane rotations (Section
+    5.3): the same emission, the other transform family."""
+    from gpu_util import bits
+    from oracle import oracle as O
+    ns = 5
+    gpu = W.Generator(ns, pool_n=n, R=2, pool_dtype=W.WN_F64 if pool == "f64" else W.WN_F32,
+                      transform=W.WN_TRANSFORM_ROTATION, variate=EXP)
+    orc = O.Generator(ns, pool_n=n, R=2, pool_dtype=pool, transform=O.TRANSFORM_ROTATION,
+                      variate=1)
+    gpu.seed(13)
+    orc.seed(13)
+    per_pool = n // 2 - 1
+    print(f"exponential rotations n={n} pool={pool} out={out}", flush=True)
+    for call, counts in enumerate(([3 * per_pool + 5, 1, 0, n, 2 * per_pool],
+                                   [per_pool - 5, 7, 2 * n + 1, 0, 3])):
+        import torch
+        streams = np.arange(ns, dtype=np.uint32)[::-1].copy() if call else np.arange(ns, dtype=np.uint32)
+        y = gpu.fill(streams, counts, out)
+        torch.cuda.synchronize()
+        want = bits(orc.fill(streams, np.asarray(counts, np.uint64),
+                             {W.WN_F64: O.F64, W.WN_F32: O.F32, W.WN_BF16: O.BF16}[out]))
+        assert_bits_equal(to_numpy_bits(y), want, f"call {call}")
+    gpu.close()
+
+
+def test_rotation_family_persistent_mixed_sizes():
+    from gpu_util import bits
+    from oracle import oracle as O
+    import torch
+    sizes = np.array([64, 1024, 4096, 2048, 16384, 256, 1024, 4096], np.uint32)
+    gpu = W.Generator(len(sizes), pool_n=sizes, R=2, transform=W.WN_TRANSFORM_ROTATION,
+                      variate=EXP)
+    orc = O.Generator(len(sizes), pool_n=sizes, R=2, transform=O.TRANSFORM_ROTATION, variate=1)
+    gpu.seed(29)
+    orc.seed(29)
+    rng = np.random.default_rng(3)
+    for call in range(3):
+        order = rng.permutation(len(sizes)).astype(np.uint32)
+        counts = rng.integers(0, 40000, size=len(sizes)).astype(np.uint64)
+        print(f"exponential rotations, persistent call {call}", flush=True)
+        y = gpu.fill(order, counts, W.WN_F32)
+        torch.cuda.synchronize()
+        assert_bits_equal(to_numpy_bits(y), bits(orc.fill(order, counts, O.F32)), f"call {call}")
+    gpu.close()
