@@ -35,6 +35,29 @@ def test_mean_stddev_bit_exact(pool, out, mean, stddev):
     assert_bits_equal(g, o, "work list")
 
 
+@pytest.mark.parametrize("tune", [{}, {"group_items": 1}, {"defer_emission": 3, "lds_double_buffer": 1},
+                                  {"threads_per_stream": 128}, {"use_graph": 1}])
+def test_mean_stddev_persistent_mixed_sizes(tune):
+    # mu and sigma on the work-list and persistent forms (pools of every size
+    # class in one request, pairs of small items, the deferred items, 128-thread
+    # items where every pool is 1024 or 2048)
+    if "threads_per_stream" in tune:
+        sizes = np.array([1024, 2048] * 6, np.uint32)
+    elif "group_items" in tune:  # pairs need every large pool to be at most 4096
+        sizes = np.array([1024] * 6 + [2048, 4096, 256], np.uint32)
+    else:
+        sizes = np.array([1024, 4096, 256, 2048, 16384, 64, 1024, 1024, 4096], np.uint32)
+    p = ExtPair(len(sizes), sizes, 2, seed=8, mean=-0.75, stddev=2.0)
+    p.gpu.set_tuning(**tune)
+    rng = np.random.default_rng(17)
+    for call, out in enumerate((W.WN_F32, W.WN_BF16, W.WN_F32)):
+        order = rng.permutation(len(sizes)).astype(np.uint32)
+        counts = rng.integers(0, 30000, size=len(sizes)).astype(np.uint64)
+        print(f"mean/stddev persistent {tune} call {call}", flush=True)
+        g, o = p.fill(order, counts, out)
+        assert_bits_equal(g, o, f"{tune} call {call}")
+
+
 def test_current_pool_source_bit_exact():
     p = ExtPair(3, 4096, 2, x_current=True)
     g, o = p.fill(np.arange(3), [20000] * 3)
