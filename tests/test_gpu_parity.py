@@ -70,6 +70,22 @@ def test_fill_bit_exact(n, R, pool, out, chi2, K):
     assert_bits_equal(g, o, "second call")
 
 
+@pytest.mark.parametrize("n,R,pool", [(1024, 7, "f32"), (4096, 64, "f32"), (2048, 5, "f64"),
+                                       (256, 64, "f32")])
+@pytest.mark.parametrize("tune", [{}, {"lds_double_buffer": 1}, {"defer_emission": 0}])
+def test_many_passes_bit_exact(n, R, pool, tune):
+    # odd pass counts and the largest allowed (64): with two LDS buffers the
+    # buffer holding the pool alternates with every pass
+    ns = 4
+    p = Pair(ns, pool_n=n, R=R, pool=pool, seed=23)
+    p.gpu.set_tuning(**tune)
+    print(f"many passes n={n} R={R} pool={pool} {tune}", flush=True)
+    g, o = p.fill(np.arange(ns), [2 * (n - 1) + 9] * ns)
+    assert_bits_equal(g, o, "first call")
+    g, o = p.fill([3, 1, 0, 2], [n + 5, 0, 3 * (n - 1), 11])
+    assert_bits_equal(g, o, "second call")
+
+
 def test_split_calls_equal_one_call():
     n = 1024
     a = Pair(3, pool_n=n, R=2, seed=5)
