@@ -53,6 +53,9 @@ CASES = [
     (1024, 2, "f32", W.WN_F32, 1, 16),   # rescale off
     (1024, 2, "f32", W.WN_F32, 2, 16),   # Fisher
     (1024, 2, "f64", W.WN_F64, 3, 0),    # Wilson-Hilferty, no renormalisation
+    (1024, 2, "f32", W.WN_F32, 0, 1),    # renormalisation before every pool
+    (4096, 1, "f64", W.WN_F64, 0, 2),    # every second pool
+    (256, 3, "f32", W.WN_BF16, 0, 1),
 ]
 
 
