@@ -103,6 +103,42 @@ def test_checkpoint_reproduces_outputs():
     assert ei.value.status == W.WN_EINVAL
 
 
+@pytest.mark.parametrize("pool", ["f32", "f64"])
+def test_zero_pool_is_reported_by_sync(pool):
+    # A pool of zeros (restored from a checkpoint) has a zero sum of squares:
+    # the kernel flags it, wn_sync reports WN_EDEVICE once and clears the flag,
+    # and the other streams of the same call are untouched.
+    import struct
+    import torch
+    ns, n = 4, 1024
+    pdt = W.WN_F64 if pool == "f64" else W.WN_F32
+    g = W.Generator(ns, pool_n=n, R=2, pool_dtype=pdt)
+    g.seed(4)
+    g.fill(np.arange(ns), [1500] * ns)
+    g.sync()
+    blob = bytearray(g.save_state())
+    head, hdr = 80, 64  # checkpoint header, then one 64-byte header per stream
+    pool_off = struct.unpack_from("<Q", blob, head + 40)[0]  # stream 0's pool offset
+    at = head + ns * hdr + pool_off
+    width = 8 if pool == "f64" else 4
+    blob[at:at + n * width] = bytes(n * width)
+    ref = W.Generator(ns, pool_n=n, R=2, pool_dtype=pdt)
+    ref.seed(4)
+    ref.load_state(bytes(g.save_state()))
+    g.load_state(bytes(blob))
+    print(f"zero pool, {pool}", flush=True)
+    y = to_numpy_bits(g.fill(np.arange(ns), [3000] * ns))
+    with pytest.raises(W.WnError) as ei:
+        g.sync()
+    assert ei.value.status == W.WN_EDEVICE
+    g.sync()  # reported once
+    want = to_numpy_bits(ref.fill(np.arange(ns), [3000] * ns))
+    torch.cuda.synchronize()
+    ref.sync()
+    assert_bits_equal(y[3000:], want[3000:], "streams 1-3")
+    assert not np.array_equal(y[:3000], want[:3000])
+
+
 def test_save_before_seed_is_estate():
     g = W.Generator(2, pool_n=64, R=1)
     with pytest.raises(W.WnError) as ei:
