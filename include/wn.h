@@ -189,6 +189,11 @@ wn_status wn_seed(wn_gen *g, uint64_t seed, void *hip_stream);
  * arrays, read before the call returns.  Streams continue where the previous
  * call stopped: fill(s, a) then fill(s, b) equals fill(s, a + b) bit for bit,
  * and results never depend on batching, order or launch shape.
+ * Requests of consecutive streams streams[j] = streams[0] + j with one count
+ * and one pool size enqueue only kernels and event operations: such a call can
+ * be captured into a HIP graph, and each replay continues the streams as a
+ * call would (other request forms upload a work list and may wait on host
+ * staging, so they are not for capture).
  * Errors: WN_EINVAL (null pointer with a non-zero count, stream id out of
  * range, a stream listed twice, more than 2^56 values in one call), WN_ESTATE
  * (not seeded), WN_ENOTSUP (WN_F64 output from a binary32 pool), WN_EDEVICE

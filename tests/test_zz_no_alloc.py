@@ -2,8 +2,9 @@
 per-request partials live in a statically allocated device array), against
 wn_fill_stats on a twin generator: the same outputs bit for bit and the same
 statistics bit for bit (same kernels, same order of sums), on two calls in a
-row, the second with a smaller input; and the request forms it rejects, which
-leave the generator unchanged."""
+row, the second with a smaller input; the request forms it rejects, which
+leave the generator unchanged; and the call captured into a HIP graph (with
+wn_fill's work-list-free form), whose replays continue the streams."""
 import numpy as np
 import pytest
 
@@ -86,3 +87,45 @@ def test_noalloc_rejects_what_needs_allocation():
     assert_stats_equal(st_new, st_ref)
     ref.close()
     new.close()
+
+
+@pytest.mark.parametrize("what", ["noalloc", "fill"])
+def test_captured_graph_replays_continue_the_streams(what):
+    # wn_fill_stats_noalloc (and wn_fill in its work-list-free form) under HIP
+    # stream capture: each replay of the captured call continues the streams
+    # as an eager call would, with eager work between the replays
+    import torch
+    ns, per, n = 64, 4096, 1024
+    streams, counts = np.arange(ns, dtype=np.uint32), np.full(ns, per, np.uint64)
+    g = W.Generator(ns, pool_n=n, R=2)
+    ref = W.Generator(ns, pool_n=n, R=2)
+    g.seed(1)
+    ref.seed(1)
+    out = torch.empty(ns * per, device="cuda")
+    rout = torch.empty_like(out)
+    st, rst = W.Generator.stats_buffer(), W.Generator.stats_buffer()
+
+    def eager(gen, o, buf, stream=None):
+        if what == "noalloc":
+            gen.fill_stats_into(o, streams, counts, buf, stream=stream, noalloc=True)
+        else:
+            gen.fill_into(o, streams, counts, stream=stream)
+
+    eager(g, out, st)  # a call before the capture: the capture orders after it
+    eager(ref, rout, rst)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        eager(g, out, st, stream=side)
+    for rep in range(3):
+        print(f"capture {what}: replay {rep}", flush=True)
+        graph.replay()
+        torch.zeros(1 << 16, device="cuda").add_(1.0)  # eager work between replays
+        eager(ref, rout, rst)
+        torch.cuda.synchronize()
+        assert_bits_equal(to_numpy_bits(out), to_numpy_bits(rout), f"replay {rep}")
+        if what == "noalloc":
+            assert_stats_equal(W.Generator.read_stats(st), W.Generator.read_stats(rst))
+    g.sync()
+    ref.sync()
