@@ -81,3 +81,18 @@ def test_lds_poisoned_build_matches_the_oracle():
     print(r.stdout[-3000:])
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert "poisoned parity ok" in r.stdout
+
+
+def test_lds_poisoned_build_random_combinations():
+    # the seeded cross-feature sweeps (outputs, and statistics) on the debug
+    # library, in a child test run
+    lib = os.path.join(ROOT, "paper_1005_2314_amd", "libwn_poison.so")
+    assert os.path.exists(lib), "build the debug library first (build.build(poison=True))"
+    env = dict(os.environ, WN_LDS_POISON="1")
+    files = [os.path.join(ROOT, "tests", f) for f in ("test_gpu_combinations.py",
+                                                       "test_gpu_stats_combinations.py")]
+    r = subprocess.run([sys.executable, "-u", "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        *files], env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    print(r.stdout[-2000:])
+    assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
+    assert " passed" in r.stdout
