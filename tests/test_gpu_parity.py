@@ -182,6 +182,36 @@ def test_two_streams_ordering():
     assert_bits_equal(to_numpy_bits(b), ob, "second stream")
 
 
+def test_two_generators_interleaved_on_two_streams():
+    """Two generators (mixed pool sizes, work lists, persistent launches, one
+    with graph replay) called alternately on two HIP streams with no host
+    synchronisation in between: each generator's calls stay ordered, the two
+    share nothing, and every output equals its oracle's."""
+    import torch
+    from gpu_util import to_numpy_bits
+    sa = np.array([64, 1024, 4096, 2048, 16384, 256, 1024], np.uint32)
+    sb = np.array([1024] * 8 + [4096], np.uint32)
+    pa = Pair(len(sa), pool_n=sa, R=2, seed=61)
+    pb = Pair(len(sb), pool_n=sb, R=3, pool="f64", seed=62)
+    pa.gpu.set_tuning(use_graph=1)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    rng = np.random.default_rng(8)
+    done = []
+    for rnd in range(6):
+        for p, sizes in ((pa, sa), (pb, sb)):
+            st = s1 if (rnd + (p is pb)) % 2 == 0 else s2
+            order = rng.permutation(len(sizes)).astype(np.uint32)
+            counts = rng.integers(0, 20000, size=len(sizes)).astype(np.uint64)
+            with torch.cuda.stream(st):
+                y = p.gpu.fill(order, counts, stream=st)
+            done.append((p, order, counts, y))
+    torch.cuda.synchronize()
+    for i, (p, order, counts, y) in enumerate(done):
+        assert_bits_equal(to_numpy_bits(y), bits(p.orc.fill(order, counts)), f"call {i}")
+    pa.gpu.sync()
+    pb.gpu.sync()
+
+
 @pytest.mark.parametrize("db,nt,oc", [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 8),
                                       (1, 0, 8), (0, 0, 6), (1, 0, 5)])
 @pytest.mark.parametrize("n,out", [(1024, W.WN_F32), (2048, W.WN_BF16), (4096, W.WN_F32),
