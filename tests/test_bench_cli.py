@@ -26,3 +26,16 @@ def test_algorithmic_bytes_of_the_bench_workload():
     assert out_b == 4 * 2**30
     assert state_b == 65536 * 2 * (4096 * 4 + 64)
     assert out_b + state_b == 6450839552
+
+
+def test_traffic_is_reported_only_for_the_profiled_sources(monkeypatch, tmp_path):
+    # the committed HBM-traffic profile matches the kernel sources as they are;
+    # a changed source makes the bench report no traffic rather than a stale one
+    sys.path.insert(0, ROOT)
+    import bench
+    t = bench.measured_traffic()
+    assert t is not None and abs(t / 6450839552 - 1) < 0.01
+    changed = tmp_path / "wn_device.hpp"
+    changed.write_bytes(open(bench.FILL_SOURCES[0], "rb").read() + b"\n// changed\n")
+    monkeypatch.setattr(bench, "FILL_SOURCES", [str(changed)] + bench.FILL_SOURCES[1:])
+    assert bench.measured_traffic() is None
